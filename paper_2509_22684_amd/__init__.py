@@ -1,0 +1,27 @@
+"""MI355X-native NTT and Groth16 quotient library (Python binding).
+
+The compute path is the HIP library ``libzkntt.so`` built from ``csrc/``
+(``python -m paper_2509_22684_amd.build``).  This package only marshals
+arguments to its C ABI (``include/zkntt.h``): torch tensors supply device
+memory and streams, and every step of every transform runs in the library's
+kernels.  There is no fallback: if the library is missing, importing the
+binding raises.
+"""
+from ._lib import (  # noqa: F401
+    FIELDS,
+    Plan,
+    ZkError,
+    lib,
+    ntt_coset_forward,
+    ntt_coset_inverse,
+    ntt_forward,
+    ntt_inverse,
+    ntt_plan_create,
+    ntt_plan_destroy,
+    ntt_plan_device_bytes,
+    ntt_plan_passes,
+    ntt_workspace_bytes,
+    quotient_poly,
+    quotient_workspace_bytes,
+    zk_last_error,
+)

@@ -1,0 +1,416 @@
+// C ABI of the NTT library: plans, transforms and the quotient chain.
+//
+// A plan fixes the field and n = 2^log2n, derives the primitive root of unity
+// w_n = g^((p-1)/n) (g the smallest generator), and builds in device memory:
+//   * the inter-pass twiddle table of every pass but the first, laid out
+//     [r][j mod Ns] so that it streams coalesced beside the data it scales;
+//   * a w_R table for each radix R used by a pass (in-tile twiddles);
+//   * the coset tables g^k, n^-1 g^-k and n^-1 g^k (k < n) used to fuse the
+//     coset shifts and the 1/n scaling into the first or last pass.
+// Tables are generated on the device from four 256-entry level tables of the
+// base computed on the host, so plan creation costs milliseconds even at
+// n = 2^24.
+//
+// Transforms are sequences of Stockham passes (ntt_kernels.hip); the inverse
+// runs the forward passes on the index-reversed input, since
+// sum_i X_i w^(-ij) = sum_i X_(-i mod n) w^(ij), and scales by 1/n on the
+// last pass.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/zkntt.h"
+#include "field.hpp"
+#include "ntt_kernels.hpp"
+
+using zk::Fe;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? ZK_ENOMEM : ZK_EDEVICE;
+}
+
+enum Kind { kForward, kInverse, kCosetForward, kCosetInverse, kInverseToCoset };
+
+struct PassDesc {
+  int log_r;
+  int log_tile;
+  uint32_t log_ns;
+  Fe* tw_pass;  // null on the first pass
+  Fe* tw_r;
+};
+
+}  // namespace
+
+struct ntt_plan {
+  int field = 0;
+  uint32_t log_n = 0;
+  uint64_t n = 0;
+  int log_e = 3;
+  uint32_t flags = 0;
+  int device = 0;
+  std::vector<PassDesc> passes;
+  std::vector<void*> owned;  // device allocations
+  size_t device_bytes = 0;
+  Fe n_inv{};        // 1/n, Montgomery
+  Fe zinv{};         // 1/(g^n - 1), Montgomery
+  Fe* coset_fwd = nullptr;        // g^k
+  Fe* coset_inv = nullptr;        // n^-1 g^-k
+  Fe* inv_to_coset = nullptr;     // n^-1 g^k
+  uint32_t* d_count = nullptr;    // validation counter
+  std::mutex validate_mu;
+};
+
+namespace {
+
+template <class F>
+struct Host {
+  // levels[256 k + d] = base^(d 256^k), k < 4, d < 256
+  static std::vector<Fe> levels(const Fe& base) {
+    std::vector<Fe> lv(1024);
+    Fe step = base;
+    for (int k = 0; k < 4; ++k) {
+      Fe x = zk::mont_one<F>();
+      for (int d = 0; d < 256; ++d) {
+        lv[256 * k + d] = x;
+        x = zk::mul_portable<F>(x, step);
+      }
+      step = x;  // step^256
+    }
+    return lv;
+  }
+};
+
+struct TableBuilder {
+  ntt_plan* p;
+  hipStream_t s = nullptr;
+  std::vector<void*> scratch;
+
+  int alloc(Fe** out, uint64_t count) {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, count * sizeof(Fe));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan table)");
+    p->owned.push_back(d);
+    p->device_bytes += count * sizeof(Fe);
+    *out = static_cast<Fe*>(d);
+    return ZK_OK;
+  }
+
+  template <class F>
+  int generate(Fe* out, uint64_t count, const Fe& base, const Fe& scale, uint32_t mode, uint64_t ns,
+               uint64_t mult) {
+    std::vector<Fe> lv = Host<F>::levels(base);
+    void* d_lv = nullptr;
+    hipError_t e = hipMalloc(&d_lv, lv.size() * sizeof(Fe));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(level table)");
+    scratch.push_back(d_lv);
+    e = hipMemcpy(d_lv, lv.data(), lv.size() * sizeof(Fe), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(level table)");
+    zk::GenArgs g{};
+    g.out = out;
+    g.levels = static_cast<const Fe*>(d_lv);
+    g.scale = scale;
+    g.count = count;
+    g.ns = ns ? ns : 1;
+    g.mult = mult;
+    g.mode = mode;
+    e = zk::launch_gen(F::ID, g, s);
+    if (e != hipSuccess) return hip_fail(e, "table generation launch");
+    return ZK_OK;
+  }
+
+  ~TableBuilder() {
+    if (!scratch.empty()) {
+      (void)hipDeviceSynchronize();
+      for (void* d : scratch) (void)hipFree(d);
+    }
+  }
+};
+
+void free_plan(ntt_plan* p) {
+  if (!p) return;
+  for (void* d : p->owned) (void)hipFree(d);
+  delete p;
+}
+
+// Split log_n into passes of at most 8 stages each, larger radices first
+// (a single pass covers n <= 2^11 in one tile).
+std::vector<int> split_passes(uint32_t log_n) {
+  std::vector<int> r;
+  if (log_n <= 11) {
+    r.push_back((int)log_n);
+    return r;
+  }
+  const int P = (int)((log_n + 7) / 8);
+  const int base = (int)log_n / P, extra = (int)log_n % P;
+  for (int k = 0; k < P; ++k) r.push_back(base + (k < extra ? 1 : 0));
+  return r;
+}
+
+template <class F>
+int build_plan(ntt_plan* p) {
+  TableBuilder tb{p};
+  const uint32_t L = p->log_n;
+  const Fe w_n = zk::root_of_unity<F>((int)L);
+  const Fe one = zk::mont_one<F>();
+  const Fe g = zk::to_mont<F>(zk::fe_from_u32<F>(F::GENERATOR));
+  const Fe g_inv = zk::inv_mont<F>(g);
+  p->n_inv = zk::inv_mont<F>(zk::pow_mont_u64<F>(zk::add<F>(one, one), L));
+  {
+    Fe gn = g;
+    for (uint32_t i = 0; i < L; ++i) gn = zk::mul_portable<F>(gn, gn);  // g^n
+    p->zinv = zk::inv_mont<F>(zk::sub<F>(gn, one));
+  }
+
+  std::vector<int> radices = split_passes(L);
+  uint32_t log_ns = 0;
+  Fe* tw_r_by_log[33] = {nullptr};
+  for (size_t k = 0; k < radices.size(); ++k) {
+    PassDesc d{};
+    d.log_r = radices[k];
+    d.log_tile = (L <= 11) ? (int)L : 11;
+    d.log_ns = log_ns;
+    if (k > 0 && (uint32_t)(d.log_tile - d.log_r) > log_ns)
+      return fail(ZK_EUNSUPPORTED, "pass schedule: tile wider than the previous passes' span");
+    if (!tw_r_by_log[d.log_r]) {
+      const uint64_t R = 1ull << d.log_r;
+      Fe* t = nullptr;
+      if (int rc = tb.alloc(&t, R)) return rc;
+      Fe w_r = w_n;  // w_R = w_n^(n/R)
+      for (uint32_t i = 0; i < L - (uint32_t)d.log_r; ++i) w_r = zk::mul_portable<F>(w_r, w_r);
+      if (int rc = tb.generate<F>(t, R, w_r, one, zk::kGenPowers, 1, 0)) return rc;
+      tw_r_by_log[d.log_r] = t;
+    }
+    d.tw_r = tw_r_by_log[d.log_r];
+    if (k > 0) {
+      const uint64_t ns = 1ull << log_ns, R = 1ull << d.log_r;
+      const uint64_t count = ns * R;
+      if (int rc = tb.alloc(&d.tw_pass, count)) return rc;
+      // entry r * Ns + j' = w_n^((n / (Ns R)) r j')
+      if (int rc = tb.generate<F>(d.tw_pass, count, w_n, one, zk::kGenPassTwiddle, ns, p->n >> (log_ns + d.log_r)))
+        return rc;
+    }
+    p->passes.push_back(d);
+    log_ns += (uint32_t)d.log_r;
+  }
+
+  // Coset tables.
+  if (int rc = tb.alloc(&p->coset_fwd, p->n)) return rc;
+  if (int rc = tb.generate<F>(p->coset_fwd, p->n, g, one, zk::kGenPowers, 1, 0)) return rc;
+  if (int rc = tb.alloc(&p->coset_inv, p->n)) return rc;
+  if (int rc = tb.generate<F>(p->coset_inv, p->n, g_inv, p->n_inv, zk::kGenPowers, 1, 0)) return rc;
+  if (int rc = tb.alloc(&p->inv_to_coset, p->n)) return rc;
+  if (int rc = tb.generate<F>(p->inv_to_coset, p->n, g, p->n_inv, zk::kGenPowers, 1, 0)) return rc;
+
+  {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, 256);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(counter)");
+    p->owned.push_back(d);
+    p->d_count = static_cast<uint32_t*>(d);
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "plan table generation");
+  return ZK_OK;
+}
+
+bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
+
+int check_device(const ntt_plan* p) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device) return fail(ZK_EINVAL, "the current HIP device is not the plan's device");
+  return ZK_OK;
+}
+
+int validate_input(ntt_plan* p, const void* x, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(p->validate_mu);
+  hipError_t e = hipMemsetAsync(p->d_count, 0, sizeof(uint32_t), s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(counter)");
+  e = zk::launch_validate(p->field, static_cast<const Fe*>(x), p->n, p->d_count, s);
+  if (e != hipSuccess) return hip_fail(e, "validate launch");
+  uint32_t bad = 0;
+  e = hipMemcpyAsync(&bad, p->d_count, sizeof bad, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "validate readback");
+  if (bad) return fail(ZK_EINVAL, std::to_string(bad) + " input elements are not canonical (>= p)");
+  return ZK_OK;
+}
+
+int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, hipStream_t s) {
+  const size_t P = p->passes.size();
+  for (size_t k = 0; k < P; ++k) {
+    const PassDesc& d = p->passes[k];
+    zk::PassArgs a{};
+    a.in = static_cast<const Fe*>(k == 0 ? in : (k % 2 == 1 ? work : out));
+    a.out = static_cast<Fe*>(k + 1 == P ? out : (k % 2 == 0 ? work : out));
+    a.tw_pass = d.tw_pass;
+    a.tw_r = d.tw_r;
+    a.log_n = p->log_n;
+    a.log_ns = d.log_ns;
+    a.flags = 0;
+    if (k == 0) {
+      if (kind == kInverse || kind == kCosetInverse || kind == kInverseToCoset) a.flags |= zk::kPassReverseIn;
+      if (kind == kCosetForward) {
+        a.flags |= zk::kPassPreTable;
+        a.pre_table = p->coset_fwd;
+      }
+    }
+    if (k + 1 == P) {
+      if (kind == kInverse) {
+        a.flags |= zk::kPassPostConst;
+        a.post_const = p->n_inv;
+      } else if (kind == kCosetInverse) {
+        a.flags |= zk::kPassPostTable;
+        a.post_table = p->coset_inv;
+      } else if (kind == kInverseToCoset) {
+        a.flags |= zk::kPassPostTable;
+        a.post_table = p->inv_to_coset;
+      }
+    }
+    hipError_t e = zk::launch_pass(p->field, d.log_r, d.log_tile, p->log_e, a, s);
+    if (e != hipSuccess) return hip_fail(e, "NTT pass launch");
+  }
+  return ZK_OK;
+}
+
+size_t workspace_elems(const ntt_plan* p) { return p->passes.size() >= 2 ? p->n : 0; }
+
+int transform_entry(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, void* stream) {
+  if (!p) return fail(ZK_EINVAL, "null plan");
+  if (!in || !out) return fail(ZK_EINVAL, "null vector pointer");
+  if (!aligned(in) || !aligned(out)) return fail(ZK_EINVAL, "vector pointers must be 256-byte aligned");
+  if (workspace_elems(p)) {
+    if (!work) return fail(ZK_EINVAL, "this plan needs a workspace (ntt_workspace_bytes)");
+    if (!aligned(work)) return fail(ZK_EINVAL, "workspace must be 256-byte aligned");
+    if (work == in || work == out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
+  }
+  if (int rc = check_device(p)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->flags & ZK_FLAG_VALIDATE) {
+    if (int rc = validate_input(const_cast<ntt_plan*>(p), in, s)) return rc;
+  }
+  return run_transform(p, kind, in, out, work, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_opts* opts) {
+  if (!out) return fail(ZK_EINVAL, "null output pointer");
+  *out = nullptr;
+  int adicity = 0;
+  if (field == ZK_FIELD_BLS12_381_FR) adicity = zk::Bls12_381Fr::TWO_ADICITY;
+  else if (field == ZK_FIELD_BN254_FR) adicity = zk::Bn254Fr::TWO_ADICITY;
+  else return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
+  if (log2n > (uint32_t)adicity)
+    return fail(ZK_EUNSUPPORTED, "log2n " + std::to_string(log2n) + " exceeds the field's 2-adicity " +
+                                     std::to_string(adicity));
+  ntt_plan_opts o{};
+  if (opts) o = *opts;
+  if (o.twiddle_mode > 1) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0 or 1");
+  if (!(o.log2_radix == 0 || o.log2_radix == 1 || o.log2_radix == 3))
+    return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1 or 3");
+  if (!(o.log2_tile == 0 || o.log2_tile == 11)) return fail(ZK_EUNSUPPORTED, "log2_tile must be 0 or 11");
+  if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
+
+  ntt_plan* p = new (std::nothrow) ntt_plan();
+  if (!p) return fail(ZK_ENOMEM, "host allocation failed");
+  p->field = field;
+  p->log_n = log2n;
+  p->n = 1ull << log2n;
+  p->log_e = o.log2_radix ? (int)o.log2_radix : 3;
+  p->flags = o.flags;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "hipGetDevice");
+  }
+  int rc = field == ZK_FIELD_BLS12_381_FR ? build_plan<zk::Bls12_381Fr>(p) : build_plan<zk::Bn254Fr>(p);
+  if (rc) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return ZK_OK;
+}
+
+void ntt_plan_destroy(ntt_plan* p) { free_plan(p); }
+
+size_t ntt_workspace_bytes(const ntt_plan* p) { return p ? workspace_elems(p) * sizeof(Fe) : 0; }
+
+size_t ntt_plan_device_bytes(const ntt_plan* p) { return p ? p->device_bytes : 0; }
+
+int ntt_plan_passes(const ntt_plan* p) { return p ? (int)p->passes.size() : 0; }
+
+int ntt_forward(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  return transform_entry(p, kForward, d_in, d_out, d_work, stream);
+}
+
+int ntt_inverse(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  return transform_entry(p, kInverse, d_in, d_out, d_work, stream);
+}
+
+int ntt_coset_forward(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  return transform_entry(p, kCosetForward, d_in, d_out, d_work, stream);
+}
+
+int ntt_coset_inverse(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  return transform_entry(p, kCosetInverse, d_in, d_out, d_work, stream);
+}
+
+size_t quotient_workspace_bytes(const ntt_plan* p) {
+  return p ? (2 * p->n + workspace_elems(p)) * sizeof(Fe) : 0;
+}
+
+int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_H, void* d_work,
+                  void* stream) {
+  if (!p) return fail(ZK_EINVAL, "null plan");
+  if (!d_A || !d_B || !d_C || !d_H || !d_work) return fail(ZK_EINVAL, "null pointer");
+  if (!aligned(d_A) || !aligned(d_B) || !aligned(d_C) || !aligned(d_H) || !aligned(d_work))
+    return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
+  if (d_H == d_A || d_H == d_B || d_H == d_C || d_work == d_H)
+    return fail(ZK_EINVAL, "H must not alias A, B, C or the workspace");
+  if (int rc = check_device(p)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->flags & ZK_FLAG_VALIDATE) {
+    for (const void* x : {d_A, d_B, d_C})
+      if (int rc = validate_input(const_cast<ntt_plan*>(p), x, s)) return rc;
+  }
+  Fe* t1 = static_cast<Fe*>(d_work);
+  Fe* t2 = t1 + p->n;
+  Fe* w = workspace_elems(p) ? t2 + p->n : nullptr;
+  Fe* H = static_cast<Fe*>(d_H);
+  // Each of A, B, C: INTT with the coset shift g^k and 1/n fused in its last
+  // pass, then a forward NTT: evaluations on g<w>.
+  const void* src[3] = {d_A, d_B, d_C};
+  Fe* dst[3] = {t1, t2, H};
+  for (int v = 0; v < 3; ++v) {
+    if (int rc = run_transform(p, kInverseToCoset, src[v], dst[v], w, s)) return rc;
+    if (int rc = run_transform(p, kForward, dst[v], dst[v], w, s)) return rc;
+  }
+  hipError_t e = zk::launch_quotient_pointwise(p->field, t1, t2, H, H, p->zinv, p->n, s);
+  if (e != hipSuccess) return hip_fail(e, "pointwise launch");
+  return run_transform(p, kCosetInverse, H, H, w, s);
+}
+
+const char* zk_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+// Prime-field arithmetic for 255-bit scalar fields on gfx950.
+//
+// An element is eight 32-bit limbs, little-endian (limb 0 least
+// significant), in Montgomery form with R = 2^256, canonical in [0, p).
+//
+// The paper's finite-field layer (Section IV-B) names the operations used by
+// the NTT butterflies: FF_add, FF_sub and FF_mul, with FF_mul and FF_sqr
+// taking almost all of the NTT's time.  It attributes most of the add/sub
+// latency to the branches that decide the conditional reduction (Section
+// IV-B1 and the micro-architecture analysis of Section IV-C); here every
+// reduction is a branchless borrow-select, so the lanes of a wavefront never
+// diverge.
+//
+// FF_mul on the device is Montgomery multiplication in the finely integrated
+// product scanning (FIPS) order of Koc, Acar and Kaliski, "Analyzing and
+// comparing Montgomery multiplication algorithms" (IEEE Micro, 1996): the
+// 512-bit product and the reduction m * p are accumulated column by column in
+// a 64-bit accumulator plus a small overflow counter.  Each 32x32-bit partial
+// product is one v_mad_u64_u32 whose carry-out goes straight into the counter
+// with v_addc_co_u32, so a column costs two instructions per partial product
+// and no compare/select.  On gfx950 v_mad_u64_u32 issues at the full VALU
+// rate, so instruction count, not multiplier throughput, sets the cost.
+//
+// The portable CIOS form (mul_portable) runs on the host for plan-time
+// constants; both forms compute the same canonical result.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace zk {
+
+constexpr int kLimbs = 8;
+
+// BLS12-381 scalar field Fr.  2-adicity 32; 7 generates the multiplicative group.
+struct Bls12_381Fr {
+  static constexpr uint32_t P[kLimbs] = {0x00000001u, 0xffffffffu, 0xfffe5bfeu, 0x53bda402u,
+                                         0x09a1d805u, 0x3339d808u, 0x299d7d48u, 0x73eda753u};
+  static constexpr uint32_t INV = 0xffffffffu;  // -p^{-1} mod 2^32
+  static constexpr int TWO_ADICITY = 32;
+  static constexpr uint32_t GENERATOR = 7;
+  static constexpr int ID = 1;
+};
+
+// BN254 scalar field Fr.  2-adicity 28; 5 generates the multiplicative group.
+struct Bn254Fr {
+  static constexpr uint32_t P[kLimbs] = {0xf0000001u, 0x43e1f593u, 0x79b97091u, 0x2833e848u,
+                                         0x8181585du, 0xb85045b6u, 0xe131a029u, 0x30644e72u};
+  static constexpr uint32_t INV = 0xefffffffu;
+  static constexpr int TWO_ADICITY = 28;
+  static constexpr uint32_t GENERATOR = 5;
+  static constexpr int ID = 2;
+};
+
+struct __align__(16) Fe {
+  uint32_t v[kLimbs];
+};
+
+__host__ __device__ __forceinline__ Fe fe_zero() {
+  Fe r;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) r.v[j] = 0;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// FF_add / FF_sub (branchless)
+
+// a + b mod p, inputs canonical.  a + b < 2p < 2^256 for both fields, so the
+// sum fits in eight limbs; subtract p and keep the difference unless it
+// borrowed.
+template <class F>
+__host__ __device__ __forceinline__ Fe add(const Fe& a, const Fe& b) {
+  Fe s, d;
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t t = (uint64_t)a.v[j] + b.v[j] + c;
+    s.v[j] = (uint32_t)t;
+    c = (uint32_t)(t >> 32);
+  }
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t t = (uint64_t)s.v[j] - F::P[j] - br;
+    d.v[j] = (uint32_t)t;
+    br = (uint32_t)(t >> 32) & 1u;
+  }
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = br ? s.v[j] : d.v[j];
+  return d;
+}
+
+// a - b mod p, inputs canonical: subtract, then add p back under the borrow
+// mask.
+template <class F>
+__host__ __device__ __forceinline__ Fe sub(const Fe& a, const Fe& b) {
+  Fe d;
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t t = (uint64_t)a.v[j] - b.v[j] - br;
+    d.v[j] = (uint32_t)t;
+    br = (uint32_t)(t >> 32) & 1u;
+  }
+  const uint32_t mask = 0u - br;
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t t = (uint64_t)d.v[j] + (F::P[j] & mask) + c;
+    d.v[j] = (uint32_t)t;
+    c = (uint32_t)(t >> 32);
+  }
+  return d;
+}
+
+// t < 2p in eight limbs -> t mod p.
+template <class F>
+__host__ __device__ __forceinline__ Fe reduce_once(const uint32_t t[kLimbs]) {
+  Fe r, d;
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t s = (uint64_t)t[j] - F::P[j] - br;
+    d.v[j] = (uint32_t)s;
+    br = (uint32_t)(s >> 32) & 1u;
+  }
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) r.v[j] = br ? t[j] : d.v[j];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// FF_mul, portable CIOS (host; also valid on the device)
+
+// Montgomery product a b 2^-256 mod p in CIOS order with the multiplication
+// and reduction loops fused.  Both moduli have a top limb below 2^31 - 1, so
+// the running value never needs a ninth limb.
+template <class F>
+__host__ __device__ __forceinline__ Fe mul_portable(const Fe& a, const Fe& b) {
+  uint32_t t[kLimbs];
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) t[j] = 0;
+#pragma unroll
+  for (int i = 0; i < kLimbs; ++i) {
+    const uint32_t bi = b.v[i];
+    uint64_t x = (uint64_t)a.v[0] * bi + t[0];
+    uint32_t A = (uint32_t)(x >> 32);
+    const uint32_t t0 = (uint32_t)x;
+    const uint32_t m = t0 * F::INV;
+    uint64_t y = (uint64_t)m * F::P[0] + t0;
+    uint32_t C = (uint32_t)(y >> 32);
+#pragma unroll
+    for (int j = 1; j < kLimbs; ++j) {
+      x = (uint64_t)a.v[j] * bi + t[j] + A;
+      A = (uint32_t)(x >> 32);
+      y = (uint64_t)m * F::P[j] + (uint32_t)x + C;
+      C = (uint32_t)(y >> 32);
+      t[j - 1] = (uint32_t)y;
+    }
+    t[kLimbs - 1] = C + A;
+  }
+  return reduce_once<F>(t);
+}
+
+// ---------------------------------------------------------------------------
+// FF_mul, device FIPS
+
+#if defined(__HIP_DEVICE_COMPILE__)
+// 64-bit acc + a * b with the carry-out of the 64-bit addition returned as a
+// lane mask.  Register-only arithmetic; no memory operand.
+__device__ __forceinline__ uint64_t mad_co_vv(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+// Same, with b wave-uniform (an SGPR operand, e.g. a modulus limb).
+__device__ __forceinline__ uint64_t mad_co_vs(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+// x + (carry bit of this lane)
+__device__ __forceinline__ uint32_t add_carry(uint32_t x, uint64_t ci) {
+  uint32_t r;
+  uint64_t unused;
+  asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(unused) : "v"(x), "s"(ci));
+  return r;
+}
+
+template <class F>
+__device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
+  uint32_t m[kLimbs], r[kLimbs];
+  uint64_t acc = 0;  // current column, low 64 bits
+  uint32_t hi = 0;   // overflow count of the current column
+#define ZK_TERM(x, y)                 \
+  {                                   \
+    uint64_t co;                      \
+    acc = mad_co_vv(x, y, acc, co);   \
+    hi = add_carry(hi, co);           \
+  }
+#define ZK_TERM_P(x, y)               \
+  {                                   \
+    uint64_t co;                      \
+    acc = mad_co_vs(x, y, acc, co);   \
+    hi = add_carry(hi, co);           \
+  }
+  // Columns 0..7: the reduction digit m_i is chosen so that column i becomes
+  // 0 mod 2^32 and is shifted out.
+#pragma unroll
+  for (int i = 0; i < kLimbs; ++i) {
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      ZK_TERM(a.v[j], b.v[i - j]);
+      ZK_TERM_P(m[j], F::P[i - j]);
+    }
+    ZK_TERM(a.v[i], b.v[0]);
+    m[i] = (uint32_t)acc * F::INV;
+    ZK_TERM_P(m[i], F::P[0]);
+    acc = (acc >> 32) | ((uint64_t)hi << 32);
+    hi = 0;
+  }
+  // Columns 8..15 hold the result.
+#pragma unroll
+  for (int i = kLimbs; i < 2 * kLimbs; ++i) {
+#pragma unroll
+    for (int j = i - (kLimbs - 1); j < kLimbs; ++j) {
+      ZK_TERM(a.v[j], b.v[i - j]);
+      ZK_TERM_P(m[j], F::P[i - j]);
+    }
+    r[i - kLimbs] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)hi << 32);
+    hi = 0;
+  }
+#undef ZK_TERM
+#undef ZK_TERM_P
+  return reduce_once<F>(r);  // the result is below 2p
+}
+#else
+// Host compilation pass: device code is parsed but never emitted here.
+template <class F>
+__host__ __device__ inline Fe mul(const Fe& a, const Fe& b) {
+  return mul_portable<F>(a, b);
+}
+#endif
+
+// ---------------------------------------------------------------------------
+// Host-side helpers for plan-time constants (plain integers <-> Montgomery).
+
+template <class F>
+inline Fe fe_from_u32(uint32_t x) {
+  Fe r = fe_zero();
+  r.v[0] = x;
+  return r;
+}
+
+// 2^256 mod p, i.e. the Montgomery form of 1, by 256 modular doublings of 1.
+template <class F>
+inline Fe mont_one() {
+  Fe x = fe_from_u32<F>(1);
+  for (int i = 0; i < 256; ++i) x = add<F>(x, x);
+  return x;
+}
+
+// 2^512 mod p: 256 more doublings.
+template <class F>
+inline Fe mont_r2() {
+  Fe x = mont_one<F>();
+  for (int i = 0; i < 256; ++i) x = add<F>(x, x);
+  return x;
+}
+
+template <class F>
+inline Fe to_mont(const Fe& plain) {
+  return mul_portable<F>(plain, mont_r2<F>());
+}
+
+template <class F>
+inline Fe from_mont(const Fe& m) {
+  return mul_portable<F>(m, fe_from_u32<F>(1));
+}
+
+// base^e (Montgomery in and out); e given as eight 32-bit limbs.
+template <class F>
+inline Fe pow_mont(const Fe& base, const uint32_t e[kLimbs]) {
+  Fe r = mont_one<F>();
+  for (int i = 255; i >= 0; --i) {
+    r = mul_portable<F>(r, r);
+    if ((e[i / 32] >> (i % 32)) & 1u) r = mul_portable<F>(r, base);
+  }
+  return r;
+}
+
+template <class F>
+inline Fe pow_mont_u64(const Fe& base, uint64_t e) {
+  uint32_t ew[kLimbs] = {(uint32_t)e, (uint32_t)(e >> 32), 0, 0, 0, 0, 0, 0};
+  return pow_mont<F>(base, ew);
+}
+
+// a^(p-2) = a^-1 (Fermat), Montgomery in and out.
+template <class F>
+inline Fe inv_mont(const Fe& a) {
+  uint32_t e[kLimbs];
+  uint32_t br = 2;
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t t = (uint64_t)F::P[j] - br;
+    e[j] = (uint32_t)t;
+    br = (uint32_t)(t >> 32) & 1u;
+  }
+  return pow_mont<F>(a, e);
+}
+
+// Primitive 2^log2n-th root of unity g^((p-1)/2^log2n) in Montgomery form.
+template <class F>
+inline Fe root_of_unity(int log2n) {
+  uint32_t e[kLimbs];
+  for (int j = 0; j < kLimbs; ++j) e[j] = F::P[j];
+  e[0] -= 1;
+  for (int s = 0; s < log2n; ++s)
+    for (int j = 0; j < kLimbs; ++j) e[j] = (e[j] >> 1) | (j + 1 < kLimbs ? e[j + 1] << 31 : 0u);
+  return pow_mont<F>(to_mont<F>(fe_from_u32<F>(F::GENERATOR)), e);
+}
+
+}  // namespace zk

@@ -1,0 +1,105 @@
+// Auxiliary kernels (table generation, pointwise quotient, validation) and
+// the pass dispatcher.  The pass kernels themselves are instantiated per
+// field and in-register radix in ntt_pass_<field>_e<k>.hip so they compile in
+// parallel.
+#include "ntt_kernels.hpp"
+#include "ntt_pass_impl.hpp"
+
+namespace zk {
+
+hipError_t launch_pass_bls_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bls_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bn_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bn_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+
+namespace {
+using detail::load_fe;
+using detail::store_fe;
+
+// ---------------------------------------------------------------------------
+// Table generation, pointwise quotient, validation
+
+template <class F>
+__global__ void __launch_bounds__(256) gen_kernel(GenArgs g) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.count) return;
+  uint64_t e = t;
+  if (g.mode == kGenPassTwiddle) e = g.mult * (t / g.ns) * (t % g.ns);
+  Fe x = g.scale;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t d = (uint32_t)(e >> (8 * k)) & 255u;
+    if (d) x = mul<F>(x, g.levels[256 * k + d]);
+  }
+  store_fe(g.out, t, x);
+}
+
+template <class F>
+__global__ void __launch_bounds__(256) quotient_pointwise_kernel(const Fe* __restrict__ a, const Fe* __restrict__ b,
+                                                                  const Fe* c, Fe* out, Fe zinv, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Fe ab = mul<F>(load_fe(a, i), load_fe(b, i));
+  store_fe(out, i, mul<F>(sub<F>(ab, load_fe(c, i)), zinv));
+}
+
+template <class F>
+__global__ void __launch_bounds__(256) validate_kernel(const Fe* __restrict__ x, uint64_t n, uint32_t* count) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Fe v = load_fe(x, i);
+  uint32_t br = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) {
+    uint64_t s = (uint64_t)v.v[j] - F::P[j] - br;
+    br = (uint32_t)(s >> 32) & 1u;
+  }
+  if (!br) atomicAdd(count, 1u);  // v >= p
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const PassArgs& a, hipStream_t s) {
+  if (field == Bls12_381Fr::ID) {
+    if (log_e == 3) return launch_pass_bls_e3(log_r, log_tile, a, s);
+    if (log_e == 1) return launch_pass_bls_e1(log_r, log_tile, a, s);
+  } else if (field == Bn254Fr::ID) {
+    if (log_e == 3) return launch_pass_bn_e3(log_r, log_tile, a, s);
+    if (log_e == 1) return launch_pass_bn_e1(log_r, log_tile, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gen(int field, const GenArgs& g, hipStream_t s) {
+  if (g.count == 0) return hipSuccess;
+  const dim3 grid(blocks_for(g.count, 256)), block(256);
+  if (field == Bls12_381Fr::ID) hipLaunchKernelGGL(gen_kernel<Bls12_381Fr>, grid, block, 0, s, g);
+  else if (field == Bn254Fr::ID) hipLaunchKernelGGL(gen_kernel<Bn254Fr>, grid, block, 0, s, g);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_quotient_pointwise(int field, const Fe* a, const Fe* b, const Fe* c, Fe* out, Fe zinv, uint64_t n,
+                                     hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(n, 256)), block(256);
+  if (field == Bls12_381Fr::ID)
+    hipLaunchKernelGGL(quotient_pointwise_kernel<Bls12_381Fr>, grid, block, 0, s, a, b, c, out, zinv, n);
+  else if (field == Bn254Fr::ID)
+    hipLaunchKernelGGL(quotient_pointwise_kernel<Bn254Fr>, grid, block, 0, s, a, b, c, out, zinv, n);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(int field, const Fe* x, uint64_t n, uint32_t* d_count, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(n, 256)), block(256);
+  if (field == Bls12_381Fr::ID) hipLaunchKernelGGL(validate_kernel<Bls12_381Fr>, grid, block, 0, s, x, n, d_count);
+  else if (field == Bn254Fr::ID) hipLaunchKernelGGL(validate_kernel<Bn254Fr>, grid, block, 0, s, x, n, d_count);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace zk

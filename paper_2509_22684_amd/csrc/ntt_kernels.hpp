@@ -1,0 +1,63 @@
+// Device kernels of the NTT library and their launch helpers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "field.hpp"
+
+namespace zk {
+
+// Flags of one global pass.
+enum PassFlags : uint32_t {
+  kPassReverseIn = 1u,   // first pass: read input index (n - idx) mod n
+  kPassPreTable = 2u,    // first pass: multiply input idx by pre_table[idx]
+  kPassPostTable = 4u,   // last pass: multiply output k by post_table[k]
+  kPassPostConst = 8u,   // last pass: multiply every output by post_const
+};
+
+// Arguments of one global radix-R Stockham pass over n = 2^log_n elements.
+// The pass reads columns j + r (n/R) for r < R, multiplies element r of
+// column j by the inter-pass twiddle w_{Ns R}^(r (j mod Ns)), runs an R-point
+// DFT, and writes output r of column j to (j / Ns) Ns R + (j mod Ns) + r Ns,
+// where Ns = 2^log_ns is the product of the radices of the earlier passes.
+struct PassArgs {
+  const Fe* in;
+  Fe* out;
+  const Fe* tw_pass;     // [r * Ns + (j mod Ns)], null on the first pass
+  const Fe* tw_r;        // w_R^k for k < R
+  const Fe* pre_table;   // see kPassPreTable
+  const Fe* post_table;  // see kPassPostTable
+  Fe post_const;         // see kPassPostConst
+  uint32_t log_n;
+  uint32_t log_ns;
+  uint32_t flags;
+};
+
+// Launch one pass; log_r + log_j = log_tile.  Returns hipSuccess or the
+// launch error.
+hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const PassArgs& a, hipStream_t s);
+
+// Table generation: out[t] = scale * base^e(t) for t < count, with
+// e(t) = t (kGenPowers) or e(t) = mult * (t / ns) * (t mod ns) (kGenPassTwiddle).
+// base^e is assembled from four 256-entry level tables held in `levels`
+// (levels[256 k + d] = base^(d 256^k)), so e must be below 2^32.
+enum GenMode : uint32_t { kGenPowers = 0, kGenPassTwiddle = 1 };
+struct GenArgs {
+  Fe* out;
+  const Fe* levels;
+  Fe scale;
+  uint64_t count;
+  uint64_t ns;
+  uint64_t mult;
+  uint32_t mode;
+};
+hipError_t launch_gen(int field, const GenArgs& g, hipStream_t s);
+
+// E_i = (A_i B_i - C_i) * zinv, written to out (may alias c).
+hipError_t launch_quotient_pointwise(int field, const Fe* a, const Fe* b, const Fe* c, Fe* out, Fe zinv, uint64_t n,
+                                     hipStream_t s);
+
+// Count elements with limbs >= p (non-canonical) into *d_count (device u32).
+hipError_t launch_validate(int field, const Fe* x, uint64_t n, uint32_t* d_count, hipStream_t s);
+
+}  // namespace zk

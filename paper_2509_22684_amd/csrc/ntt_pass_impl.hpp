@@ -1,0 +1,285 @@
+// NTT pass kernels for gfx950.
+//
+// The transform follows the paper's description of GPU NTTs (Section II-C):
+// radix-2 Cooley-Tukey butterflies, with a block of threads performing a
+// radix-2^k sub-transform through on-chip shared memory and several stages
+// processed per batch.  Here each workgroup runs one radix-R "pass" of a
+// Stockham (self-sorting) decomposition over a tile of J columns x R points:
+//
+//   * global memory is touched once per pass, by coalesced loads of J
+//     consecutive columns (J x 32 bytes per row) and coalesced stores, so no
+//     separate bit-reversal or shuffle pass exists and input and output are
+//     in natural order;
+//   * inside the tile, every thread keeps E = 8 elements in registers and
+//     runs radix-8 DIT butterflies on them; rounds of radix-8 are separated
+//     by one exchange through LDS (padded so 32-byte elements do not
+//     conflict on banks);
+//   * the twiddles between passes come from a table laid out in the order
+//     the pass reads its data ([r][j mod Ns]), so they stream coalesced
+//     alongside it; in-tile twiddles come from a small w_R table.
+//
+// All arithmetic is exact and branchless (see field.hpp).
+#pragma once
+#include <utility>
+
+#include "ntt_kernels.hpp"
+
+namespace zk {
+namespace detail {
+
+constexpr __host__ __device__ int imin(int a, int b) { return a < b ? a : b; }
+
+__device__ __forceinline__ Fe load_fe(const Fe* __restrict__ p, uint64_t i) {
+  const uint4* q = reinterpret_cast<const uint4*>(p + i);
+  uint4 lo = q[0], hi = q[1];
+  Fe r;
+  r.v[0] = lo.x; r.v[1] = lo.y; r.v[2] = lo.z; r.v[3] = lo.w;
+  r.v[4] = hi.x; r.v[5] = hi.y; r.v[6] = hi.z; r.v[7] = hi.w;
+  return r;
+}
+
+__device__ __forceinline__ void store_fe(Fe* __restrict__ p, uint64_t i, const Fe& x) {
+  uint4* q = reinterpret_cast<uint4*>(p + i);
+  q[0] = make_uint4(x.v[0], x.v[1], x.v[2], x.v[3]);
+  q[1] = make_uint4(x.v[4], x.v[5], x.v[6], x.v[7]);
+}
+
+// LDS slot of element e of a tile: one pad slot after every 8 elements, so
+// lanes writing elements 8 apart land 9 slots (288 bytes) apart and spread
+// over all banks.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t e) { return e + (e >> 3); }
+
+constexpr __host__ __device__ int bitrev_ct(int x, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((x >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// Compile-time loop: fn(std::integral_constant<int, i>) for i < N, so every
+// register-array index below is a constant and the arrays stay in VGPRs.
+template <class Fn, int... I>
+__device__ __forceinline__ void sfor_impl(Fn& fn, std::integer_sequence<int, I...>) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void sfor(Fn&& fn) {
+  sfor_impl(fn, std::make_integer_sequence<int, N>{});
+}
+
+// In-register DFT of E = 2^LOGE points (natural order in and out) on
+// v[OFF .. OFF + E): bit-reversed renaming, then log2 E radix-2 DIT stages
+// with butterflies (x, y) -> (x + w y, x - w y).  W[k] = w_E^k for k < E/2.
+template <class F, int LOGE, int OFF, int N>
+__device__ __forceinline__ void dft_regs(Fe (&v)[N], const Fe* W) {
+  constexpr int E = 1 << LOGE;
+  if constexpr (E > 1) {
+    Fe a[E];
+    sfor<E>([&](auto s_) {
+      constexpr int s = decltype(s_)::value;
+      a[s] = v[OFF + bitrev_ct(s, LOGE)];
+    });
+    sfor<LOGE>([&](auto st_) {
+      constexpr int st = decltype(st_)::value;
+      constexpr int half = 1 << st;  // butterflies pair elements half apart
+      sfor<E / 2>([&](auto u_) {
+        constexpr int u = decltype(u_)::value;
+        constexpr int t = u & (half - 1);
+        constexpr int b = (u >> st) << (st + 1);
+        Fe y = a[b + t + half];
+        if constexpr (t != 0) y = mul<F>(y, W[t << (LOGE - 1 - st)]);
+        const Fe x = a[b + t];
+        a[b + t] = add<F>(x, y);
+        a[b + t + half] = sub<F>(x, y);
+      });
+    });
+    sfor<E>([&](auto s_) {
+      constexpr int s = decltype(s_)::value;
+      v[OFF + s] = a[s];
+    });
+  }
+}
+
+template <int LOG_R, int LOG_TILE, int LOG_E>
+struct PassShape {
+  static constexpr int R = 1 << LOG_R;
+  static constexpr int LOG_J = LOG_TILE - LOG_R;
+  static constexpr int J = 1 << LOG_J;
+  static constexpr int LE = imin(LOG_E, LOG_R);  // log2 elements per thread
+  static constexpr int EL = 1 << LE;
+  static constexpr int THREADS = (1 << LOG_TILE) / EL;
+  static constexpr int ROUNDS = LOG_R == 0 ? 0 : (LOG_R + LE - 1) / LE;
+  static constexpr int LDS_SLOTS = ROUNDS > 1 ? (1 << LOG_TILE) + (1 << LOG_TILE) / 8 : 1;
+  static constexpr int SLOT_STRIDE = R / EL;  // threads per column
+  // log2 radix of in-tile round rho: full LE except possibly the last
+  static constexpr int round_log(int rho) { return imin(LE, LOG_R - rho * LE); }
+};
+
+// One in-tile round rho (radix Er = 2^LR, earlier in-tile radices' product
+// Nsr = 2^(rho LE)).  Thread q of column c owns slots i = q + g (R / EL) for
+// g < EL / Er; slot i takes points i + s (R / Er), s < Er.  Round 0 works on
+// the registers as loaded; later rounds read the tile from LDS and apply the
+// in-tile twiddles w_{Nsr Er}^(s (i mod Nsr)).  All rounds but the last write
+// their outputs (i / Nsr) Nsr Er + (i mod Nsr) + s Nsr back to LDS.
+template <class F, int LOG_R, int LOG_TILE, int LOG_E, int RHO, int N>
+__device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __restrict__ tw_r, uint32_t c,
+                                           uint32_t q) {
+  using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
+  constexpr int LOG_NSR = RHO * S::LE;
+  constexpr int LR = S::round_log(RHO);
+  constexpr int ER = 1 << LR;
+  constexpr int NSR = 1 << LOG_NSR;
+  constexpr bool LAST = RHO + 1 == S::ROUNDS;
+
+  if constexpr (RHO > 0) {
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint32_t i = q + (e / ER) * S::SLOT_STRIDE;
+      const uint32_t idx = i + (e % ER) * (S::R / ER);
+      v[e] = lds[lds_slot(idx * S::J + c)];
+    });
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      constexpr int s = e % ER;
+      if constexpr (s != 0) {
+        const uint32_t im = (q + (e / ER) * S::SLOT_STRIDE) & (NSR - 1);
+        v[e] = mul<F>(v[e], tw_r[(S::R / (NSR * ER)) * s * im]);
+      }
+    });
+  }
+  Fe W[ER / 2 > 0 ? ER / 2 : 1];
+  sfor<ER / 2>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    W[k] = tw_r[k * (S::R / ER)];  // w_Er^k, wave-uniform
+  });
+  sfor<S::EL / ER>([&](auto g_) {
+    constexpr int g = decltype(g_)::value;
+    dft_regs<F, LR, g * ER>(v, W);
+  });
+
+  if constexpr (!LAST) {
+    if constexpr (RHO > 0) __syncthreads();  // every thread has read this round's inputs
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint32_t i = q + (e / ER) * S::SLOT_STRIDE;
+      const uint32_t o = (i >> LOG_NSR) * (NSR * ER) + (i & (NSR - 1)) + (e % ER) * NSR;
+      lds[lds_slot(o * S::J + c)] = v[e];
+    });
+    __syncthreads();
+    tile_round<F, LOG_R, LOG_TILE, LOG_E, RHO + 1>(v, lds, tw_r, c, q);
+  }
+}
+
+template <class F, int LOG_R, int LOG_TILE, int LOG_E>
+__global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
+    ntt_pass_kernel(PassArgs a) {
+  using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
+  __shared__ Fe lds[S::LDS_SLOTS];
+
+  const uint32_t t = threadIdx.x;
+  const uint32_t c = t & (S::J - 1);  // column within the tile
+  const uint32_t q = t >> S::LOG_J;   // thread index within the column
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t ns = 1ull << a.log_ns;
+  const uint64_t j = (uint64_t)blockIdx.x * S::J + c;  // global column, < n / R
+  const uint32_t log_stride = a.log_n - LOG_R;         // column stride n / R
+
+  // Round 0 reads its points r = i + s (R / Er0) straight from global memory.
+  constexpr int ER0 = 1 << S::round_log(0);
+  Fe v[S::EL];
+  auto point0 = [&](int e) -> uint64_t { return q + (e / ER0) * S::SLOT_STRIDE + (e % ER0) * (S::R / ER0); };
+  const bool rev = a.flags & kPassReverseIn;
+  sfor<S::EL>([&](auto e_) {
+    constexpr int e = decltype(e_)::value;
+    const uint64_t idx = j + (point0(e) << log_stride);
+    v[e] = load_fe(a.in, rev ? ((n - idx) & (n - 1)) : idx);
+  });
+  if (a.flags & kPassPreTable) {
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      v[e] = mul<F>(v[e], load_fe(a.pre_table, j + (point0(e) << log_stride)));
+    });
+  }
+  if (a.tw_pass) {  // inter-pass twiddle w_{Ns R}^(r (j mod Ns)), table [r][j mod Ns]
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      v[e] = mul<F>(v[e], load_fe(a.tw_pass, (point0(e) << a.log_ns) + (j & (ns - 1))));
+    });
+  }
+
+  if constexpr (S::ROUNDS > 0) tile_round<F, LOG_R, LOG_TILE, LOG_E, 0>(v, lds, a.tw_r, c, q);
+
+  // The last round leaves output r_out = i + s (R / Er) of column j in
+  // v[g Er + s]; it goes to (j / Ns) Ns R + (j mod Ns) + r_out Ns.
+  constexpr int ERL = S::ROUNDS == 0 ? 1 : 1 << S::round_log(S::ROUNDS - 1);
+  const uint64_t base = ((j >> a.log_ns) << (a.log_ns + LOG_R)) + (j & (ns - 1));
+  auto out_index = [&](int e) -> uint64_t {
+    const uint64_t r_out = q + (e / ERL) * S::SLOT_STRIDE + (e % ERL) * (S::R / ERL);
+    return base + (r_out << a.log_ns);
+  };
+  if (a.flags & kPassPostTable) {
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      v[e] = mul<F>(v[e], load_fe(a.post_table, out_index(e)));
+    });
+  }
+  if (a.flags & kPassPostConst) {
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      v[e] = mul<F>(v[e], a.post_const);
+    });
+  }
+  sfor<S::EL>([&](auto e_) {
+    constexpr int e = decltype(e_)::value;
+    store_fe(a.out, out_index(e), v[e]);
+  });
+}
+
+}  // namespace detail
+}  // namespace zk
+
+namespace zk {
+namespace detail {
+
+template <class F, int LOG_R, int LOG_TILE, int LOG_E>
+hipError_t launch_one(const PassArgs& a, hipStream_t s) {
+  using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
+  const uint64_t tiles = (1ull << a.log_n) >> LOG_TILE;
+  hipLaunchKernelGGL((ntt_pass_kernel<F, LOG_R, LOG_TILE, LOG_E>), dim3((uint32_t)tiles), dim3(S::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+// Multi-pass tiles of 2^11 elements with radix 2^5 .. 2^8 per pass, and
+// single-pass transforms of up to 2^11 points held in one tile.
+template <class F, int LOG_E>
+hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_t s) {
+  if (log_tile == 11) {
+    switch (log_r) {
+      case 5: return launch_one<F, 5, 11, LOG_E>(a, s);
+      case 6: return launch_one<F, 6, 11, LOG_E>(a, s);
+      case 7: return launch_one<F, 7, 11, LOG_E>(a, s);
+      case 8: return launch_one<F, 8, 11, LOG_E>(a, s);
+      case 11: return launch_one<F, 11, 11, LOG_E>(a, s);
+      default: break;
+    }
+  }
+  if (log_tile == log_r) {
+    switch (log_r) {
+      case 0: return launch_one<F, 0, 0, LOG_E>(a, s);
+      case 1: return launch_one<F, 1, 1, LOG_E>(a, s);
+      case 2: return launch_one<F, 2, 2, LOG_E>(a, s);
+      case 3: return launch_one<F, 3, 3, LOG_E>(a, s);
+      case 4: return launch_one<F, 4, 4, LOG_E>(a, s);
+      case 5: return launch_one<F, 5, 5, LOG_E>(a, s);
+      case 6: return launch_one<F, 6, 6, LOG_E>(a, s);
+      case 7: return launch_one<F, 7, 7, LOG_E>(a, s);
+      case 8: return launch_one<F, 8, 8, LOG_E>(a, s);
+      case 9: return launch_one<F, 9, 9, LOG_E>(a, s);
+      case 10: return launch_one<F, 10, 10, LOG_E>(a, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace detail
+}  // namespace zk

@@ -1,0 +1,156 @@
+"""GPU parity: every transform of the HIP library against the CPU oracle,
+bit for bit, through the C ABI.
+
+Inputs are seeded uniform field vectors (seeded_inputs); expected values come
+from the C oracle (Barrett arithmetic, radix-2 textbook NTT), which the CPU
+suite pins to the mathematics.
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import coracle
+from tests.gpu_util import first_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["bls12_381_fr", "bn254_fr"]
+KINDS = ["forward", "inverse", "coset_forward", "coset_inverse"]
+
+
+def _plan(field, log2n, **kw):
+    from paper_2509_22684_amd import Plan
+
+    return Plan(field, log2n, **kw)
+
+
+def _run(plan, kind, x, out=None):
+    return getattr(plan, kind)(x, out=out)
+
+
+def _check(got, want, what):
+    nbad, first = first_mismatch(got, want)
+    assert nbad == 0, f"{what}: {nbad} mismatching elements, first at {first}"
+
+
+@pytest.mark.parametrize("field", FIELDS)
+@pytest.mark.parametrize("log2n", list(range(0, 13)) + [13, 14, 16, 17, 19])
+def test_all_kinds_small_and_medium(cuda, field, log2n):
+    n = 1 << log2n
+    x = si.uniform_field_vector(field, n, si.stream_seed(100 + log2n, 0, 0))
+    plan = _plan(field, log2n)
+    dx = to_dev(x, cuda)
+    for kind in KINDS:
+        got = to_host(_run(plan, kind, dx))
+        want = coracle.transform(field, kind, x)
+        _check(got, want, f"{field} 2^{log2n} {kind}")
+    assert np.array_equal(to_host(dx), x), "input was modified"
+
+
+@pytest.mark.parametrize("field", FIELDS)
+def test_size_2_20_all_kinds_and_round_trips(cuda, field):
+    """Forward, inverse and coset transforms at n = 2^20 on one seeded vector;
+    INTT(NTT(x)) = x and cosetINTT(cosetNTT(x)) = x on the GPU alone."""
+    import torch
+
+    log2n = 20
+    x = si.uniform_field_vector(field, 1 << log2n, si.stream_seed(2, 0, 0))
+    plan = _plan(field, log2n)
+    dx = to_dev(x, cuda)
+    outs = {}
+    for kind in KINDS:
+        outs[kind] = _run(plan, kind, dx)
+        _check(to_host(outs[kind]), coracle.transform(field, kind, x), f"{field} 2^20 {kind}")
+    assert torch.equal(plan.inverse(outs["forward"]), dx)
+    assert torch.equal(plan.forward(outs["inverse"]), dx)
+    assert torch.equal(plan.coset_inverse(outs["coset_forward"]), dx)
+    assert torch.equal(plan.coset_forward(outs["coset_inverse"]), dx)
+
+
+@pytest.mark.parametrize("log2n", [3, 10, 12, 16])
+def test_radix2_schedule_is_byte_identical(cuda, log2n):
+    """The radix-2 schedule (log2_radix = 1) gives the same bytes as the
+    default radix-8 schedule and the oracle."""
+    field = "bls12_381_fr"
+    x = si.uniform_field_vector(field, 1 << log2n, si.stream_seed(1, 0, 0))
+    dx = to_dev(x, cuda)
+    p8 = _plan(field, log2n)
+    p2 = _plan(field, log2n, log2_radix=1)
+    want = coracle.transform(field, "forward", x)
+    for kind in KINDS:
+        a = to_host(_run(p8, kind, dx))
+        b = to_host(_run(p2, kind, dx))
+        assert np.array_equal(a, b), f"radix-2 and radix-8 differ for {kind}"
+    _check(to_host(p2.forward(dx)), want, "radix-2 forward")
+
+
+@pytest.mark.parametrize("log2n", [5, 11, 12, 18])
+def test_in_place(cuda, log2n):
+    field = "bls12_381_fr"
+    x = si.uniform_field_vector(field, 1 << log2n, si.stream_seed(7, log2n, 0))
+    plan = _plan(field, log2n)
+    for kind in KINDS:
+        d = to_dev(x, cuda)
+        _run(plan, kind, d, out=d)
+        _check(to_host(d), coracle.transform(field, kind, x), f"in-place {kind} 2^{log2n}")
+
+
+def test_poisoned_outputs_are_fully_overwritten(cuda):
+    import torch
+
+    field, log2n = "bn254_fr", 15
+    x = si.uniform_field_vector(field, 1 << log2n, 31)
+    plan = _plan(field, log2n)
+    dx = to_dev(x, cuda)
+    out = torch.full_like(dx, -1)
+    plan.forward(dx, out=out)
+    _check(to_host(out), coracle.transform(field, "forward", x), "poisoned output")
+
+
+@pytest.mark.parametrize("field", FIELDS)
+@pytest.mark.parametrize("log2n", [0, 1, 2, 5, 9, 12, 15])
+def test_quotient_small(cuda, field, log2n):
+    n = 1 << log2n
+    A, B, C = (si.uniform_field_vector(field, n, si.stream_seed(3, log2n, v)) for v in range(3))
+    plan = _plan(field, log2n)
+    got = to_host(plan.quotient(to_dev(A, cuda), to_dev(B, cuda), to_dev(C, cuda)))
+    _check(got, coracle.quotient(field, A, B, C), f"quotient {field} 2^{log2n}")
+
+
+def test_error_codes(cuda):
+    import torch
+
+    from paper_2509_22684_amd import ZkError, ntt_forward, ntt_plan_create
+
+    with pytest.raises(ZkError) as e:
+        ntt_plan_create("bls12_381_fr", 33)
+    assert e.value.code == -2
+    with pytest.raises(ZkError) as e:
+        ntt_plan_create("bn254_fr", 29)
+    assert e.value.code == -2
+    with pytest.raises(ZkError) as e:
+        ntt_plan_create(3, 10)
+    assert e.value.code == -2
+    plan = _plan("bls12_381_fr", 14)
+    buf = torch.zeros(2 * plan.n + 8, 8, dtype=torch.int32, device=cuda)
+    work = torch.zeros(plan.n, 8, dtype=torch.int32, device=cuda)
+    with pytest.raises(ZkError) as e:  # misaligned input (32 bytes past an aligned base)
+        ntt_forward(plan.handle, buf[1:], buf[plan.n + 8:], work)
+    assert e.value.code == -1
+    with pytest.raises(ZkError) as e:  # missing workspace
+        ntt_forward(plan.handle, buf[:plan.n], buf[plan.n + 8:], None)
+    assert e.value.code == -1
+
+
+def test_validate_flag_rejects_noncanonical(cuda):
+    from paper_2509_22684_amd import Plan, ZkError
+
+    field, log2n = "bls12_381_fr", 12
+    x = si.uniform_field_vector(field, 1 << log2n, 5)
+    bad = x.copy()
+    bad[77] = np.frombuffer(si.MODULI[field].to_bytes(32, "little"), dtype="<u4")  # exactly p
+    plan = Plan(field, log2n, flags=1)
+    plan.forward(to_dev(x, cuda))  # canonical input passes
+    with pytest.raises(ZkError) as e:
+        plan.forward(to_dev(bad, cuda))
+    assert e.value.code == -1
