@@ -1,0 +1,191 @@
+"""Benchmark: Fr255 NTT throughput at n = 2^24 on one MI355X.
+
+A step is one pass of the whole hot path on one batch of synthetic input: the
+Groth16 quotient chain at n = 2^24 over BLS12-381 Fr (three inverse NTTs with
+the coset shift fused, three forward NTTs, the pointwise (A B - C)/Z_H
+product and the coset inverse NTT: seven transforms).  `value` counts NTT
+elements per second over those seven transforms: 7 * 2^24 / step time.
+
+Also reported: the single forward NTT at 2^24 (elements/s); the roofline of
+the dominant kernel (the radix-256 pass kernel, timed per launch with HIP
+events on the stream it runs on); and the CPU oracle timed on a bounded
+sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LOG2N = 24
+FIELD = "bls12_381_fr"
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; v_mad_u64_u32 issues at
+# the full VALU rate on gfx950 (one 32x32->64 multiply-add per lane per
+# cycle), so the integer multiply-add peak equals the VALU lane rate.
+PEAK_MAD_PER_S = 256 * 4 * 16 * 2.4e9
+PEAK_HBM_BYTES_PER_S = 8.0e12
+MADS_PER_FFMUL = 136  # 2 s^2 + s for s = 8 limbs (one CIOS/FIPS Montgomery product)
+KERNEL_SOURCES = ["paper_2509_22684_amd/csrc/field.hpp", "paper_2509_22684_amd/csrc/ntt_pass_impl.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(khash: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ntt_pass_r256_2e24_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != khash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x_host) -> dict:
+    """The C oracle on the host cores: one forward NTT at n = 2^24."""
+    from oracle import coracle
+
+    threads = coracle.default_threads()
+    t0 = time.perf_counter()
+    coracle.transform(FIELD, "forward", x_host, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": (1 << LOG2N) / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
+            "sample": f"one forward NTT at n=2^24 (BLS12-381 Fr) with the C oracle, {dt:.2f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(independent jobs shard across GPUs without communication).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_2509_22684_amd import Plan, ntt_profile_passes
+
+    dev = torch.device("cuda:0")
+    n = 1 << LOG2N
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int32).copy()).to(dev)
+
+    print(f"[bench] generating inputs n=2^{LOG2N}", file=sys.stderr, flush=True)
+    host = [si.uniform_field_vector(FIELD, n, si.stream_seed(3, 0, v)) for v in range(3)]
+    A, B, C = (to_dev(h) for h in host)
+    H = torch.empty_like(A)
+    plan = Plan(FIELD, LOG2N)
+    stream = torch.cuda.current_stream(dev)
+
+    # --- the step: quotient chain (7 transforms) ---
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        plan.quotient(A, B, C, H)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.quotient(A, B, C, H)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = 7 * n / (ms_per_step * 1e-3)
+
+    # --- single forward NTT at 2^24 (median of 10 after 3 warm-ups) ---
+    out = torch.empty_like(A)
+    for _ in range(3):
+        plan.forward(A, out)
+    fwd_ms = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.forward(A, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms.append(e0.elapsed_time(e1))
+    fwd_med = statistics.median(fwd_ms)
+
+    # --- dominant kernel: per-pass HIP events on the launch stream ---
+    work = plan.workspace(A)
+    per_pass = [ntt_profile_passes(plan.handle, 0, A, out, work, stream) for _ in range(5)]
+    npass = len(per_pass[0])
+    pass_ms = [statistics.median(p[k] for p in per_pass) for k in range(npass)]
+    avg_pass_ms = sum(pass_ms) / npass
+    log_r = LOG2N // npass
+    mads_per_launch = (n // 2) * log_r * MADS_PER_FFMUL  # butterflies in one pass x MADs per FF_mul
+    achieved = mads_per_launch / (avg_pass_ms * 1e-3)
+    khash = kernel_hash()
+    traffic = traffic_from_profile(khash)
+    roofline = {
+        "bound": "alu",
+        "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE=11, LOG_E=3>",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_MAD_PER_S / 1e12,
+        "unit": "T MAD/s",
+        "frac": achieved / PEAK_MAD_PER_S,
+        "traffic": traffic,
+        "avg_launch_ms": avg_pass_ms,
+        "pass_ms": pass_ms,
+        "algorithmic_mads_per_launch": mads_per_launch,
+        "hbm_gbs_min_traffic": (2 * n * 32 + (n * 32 if npass > 1 else 0)) / (avg_pass_ms * 1e-3) / 1e9,
+        "kernel_source_hash": khash,
+    }
+
+    result = {
+        "metric": "Fr255 NTT elements/s at n=2^24",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "wall_s_timed": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "groth16 quotient chain, n=2^24, BLS12-381 Fr (7 NTTs + pointwise), "
+                               "uniform random A, B, C from seed 3",
+                   "field": FIELD, "log2n": LOG2N, "transforms_per_step": 7},
+        "forward_ntt_2e24": {"ms_median": fwd_med, "elements_per_s": n / (fwd_med * 1e-3), "passes": npass},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cb = cpu_baseline(host[0])
+        result["cpu_baseline"] = cb
+        result["gpu_over_cpu_forward"] = result["forward_ntt_2e24"]["elements_per_s"] / cb["value"]
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

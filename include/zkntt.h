@@ -117,6 +117,14 @@ size_t quotient_workspace_bytes(const ntt_plan *p);
 int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_H,
                   void *d_work, void *stream);
 
+/* Measurement helper: run one transform (kind 0 forward, 1 inverse, 2 coset
+ * forward, 3 coset inverse; same buffer rules as the calls above) with a HIP
+ * event recorded on `stream` before each pass and after the last, wait for
+ * it, and store each pass's duration in ms_per_pass[0 .. passes).  Returns
+ * the number of passes (> 0) or a zk_status.  Synchronises the stream. */
+int ntt_profile_passes(const ntt_plan *p, int kind, const void *d_in, void *d_out, void *d_work, void *stream,
+                       float *ms_per_pass, int max_passes);
+
 /* Thread-local description of the calling thread's last failure. */
 const char *zk_last_error(void);
 

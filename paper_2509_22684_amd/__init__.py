@@ -20,6 +20,7 @@ from ._lib import (  # noqa: F401
     ntt_plan_destroy,
     ntt_plan_device_bytes,
     ntt_plan_passes,
+    ntt_profile_passes,
     ntt_workspace_bytes,
     quotient_poly,
     quotient_workspace_bytes,

@@ -54,6 +54,9 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ctypes.c_int
         L.quotient_poly.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.quotient_poly.restype = ctypes.c_int
+        L.ntt_profile_passes.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.c_int]
+        L.ntt_profile_passes.restype = ctypes.c_int
         L.zk_last_error.argtypes = []
         L.zk_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -147,6 +150,15 @@ def ntt_coset_inverse(plan, d_in, d_out, d_work=None, stream=None) -> None:
 def quotient_poly(plan, d_A, d_B, d_C, d_H, d_work, stream=None) -> None:
     _check(lib().quotient_poly(plan, _ptr(d_A), _ptr(d_B), _ptr(d_C), _ptr(d_H), _ptr(d_work),
                                _stream(stream, d_A)), "quotient_poly")
+
+
+def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -> list:
+    """Per-pass durations (ms) of one transform, from HIP events on `stream`."""
+    buf = (ctypes.c_float * 64)()
+    rc = lib().ntt_profile_passes(plan, kind, _ptr(d_in), _ptr(d_out), _ptr(d_work), _stream(stream, d_in), buf, 64)
+    if rc < 0:
+        _check(rc, "ntt_profile_passes")
+    return [buf[k] for k in range(rc)]
 
 
 # ---------------------------------------------------------------------------

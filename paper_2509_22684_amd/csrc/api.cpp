@@ -253,9 +253,16 @@ int validate_input(ntt_plan* p, const void* x, hipStream_t s) {
   return ZK_OK;
 }
 
-int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, hipStream_t s) {
+// events: optional array of P + 1 events recorded before each pass and
+// after the last one on stream s.
+int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, hipStream_t s,
+                  hipEvent_t* events = nullptr) {
   const size_t P = p->passes.size();
   for (size_t k = 0; k < P; ++k) {
+    if (events) {
+      hipError_t e = hipEventRecord(events[k], s);
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     const PassDesc& d = p->passes[k];
     zk::PassArgs a{};
     a.in = static_cast<const Fe*>(k == 0 ? in : (k % 2 == 1 ? work : out));
@@ -286,6 +293,10 @@ int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void*
     }
     hipError_t e = zk::launch_pass(p->field, d.log_r, d.log_tile, p->log_e, a, s);
     if (e != hipSuccess) return hip_fail(e, "NTT pass launch");
+  }
+  if (events) {
+    hipError_t e = hipEventRecord(events[P], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   }
   return ZK_OK;
 }
@@ -409,6 +420,38 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
   hipError_t e = zk::launch_quotient_pointwise(p->field, t1, t2, H, H, p->zinv, p->n, s);
   if (e != hipSuccess) return hip_fail(e, "pointwise launch");
   return run_transform(p, kCosetInverse, H, H, w, s);
+}
+
+int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_out, void* d_work, void* stream,
+                       float* ms_per_pass, int max_passes) {
+  if (!p || !ms_per_pass) return fail(ZK_EINVAL, "null argument");
+  if (kind < 0 || kind > 3) return fail(ZK_EINVAL, "kind must be 0..3");
+  const int P = (int)p->passes.size();
+  if (max_passes < P) return fail(ZK_EINVAL, "ms_per_pass holds fewer entries than the plan has passes");
+  if (!d_in || !d_out) return fail(ZK_EINVAL, "null vector pointer");
+  if (!aligned(d_in) || !aligned(d_out)) return fail(ZK_EINVAL, "vector pointers must be 256-byte aligned");
+  if (workspace_elems(p) && (!d_work || !aligned(d_work) || d_work == d_in || d_work == d_out))
+    return fail(ZK_EINVAL, "this plan needs a distinct, aligned workspace");
+  if (int rc = check_device(p)) return rc;
+  std::vector<hipEvent_t> ev(P + 1, nullptr);
+  int rc = ZK_OK;
+  for (auto& e : ev) {
+    hipError_t h = hipEventCreate(&e);
+    if (h != hipSuccess) {
+      rc = hip_fail(h, "hipEventCreate");
+      break;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!rc) rc = run_transform(p, static_cast<Kind>(kind), d_in, d_out, d_work, s, ev.data());
+  if (!rc) {
+    hipError_t h = hipEventSynchronize(ev[P]);
+    for (int k = 0; k < P && h == hipSuccess; ++k) h = hipEventElapsedTime(&ms_per_pass[k], ev[k], ev[k + 1]);
+    if (h != hipSuccess) rc = hip_fail(h, "pass timing");
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return rc ? rc : P;
 }
 
 const char* zk_last_error(void) { return g_last_error.c_str(); }

@@ -67,24 +67,16 @@ __host__ __device__ __forceinline__ Fe fe_zero() {
 
 // a + b mod p, inputs canonical.  a + b < 2p < 2^256 for both fields, so the
 // sum fits in eight limbs; subtract p and keep the difference unless it
-// borrowed.
+// borrowed.  The limb chains use the add/sub-with-carry builtins, which lower
+// to v_add_co_u32 / v_addc_co_u32 (v_sub_co / v_subb_co) chains on gfx950.
 template <class F>
 __host__ __device__ __forceinline__ Fe add(const Fe& a, const Fe& b) {
   Fe s, d;
-  uint32_t c = 0;
+  unsigned int c = 0, br = 0;
 #pragma unroll
-  for (int j = 0; j < kLimbs; ++j) {
-    uint64_t t = (uint64_t)a.v[j] + b.v[j] + c;
-    s.v[j] = (uint32_t)t;
-    c = (uint32_t)(t >> 32);
-  }
-  uint32_t br = 0;
+  for (int j = 0; j < kLimbs; ++j) s.v[j] = __builtin_addc(a.v[j], b.v[j], c, &c);
 #pragma unroll
-  for (int j = 0; j < kLimbs; ++j) {
-    uint64_t t = (uint64_t)s.v[j] - F::P[j] - br;
-    d.v[j] = (uint32_t)t;
-    br = (uint32_t)(t >> 32) & 1u;
-  }
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_subc(s.v[j], F::P[j], br, &br);
 #pragma unroll
   for (int j = 0; j < kLimbs; ++j) d.v[j] = br ? s.v[j] : d.v[j];
   return d;
@@ -95,21 +87,12 @@ __host__ __device__ __forceinline__ Fe add(const Fe& a, const Fe& b) {
 template <class F>
 __host__ __device__ __forceinline__ Fe sub(const Fe& a, const Fe& b) {
   Fe d;
-  uint32_t br = 0;
+  unsigned int br = 0, c = 0;
 #pragma unroll
-  for (int j = 0; j < kLimbs; ++j) {
-    uint64_t t = (uint64_t)a.v[j] - b.v[j] - br;
-    d.v[j] = (uint32_t)t;
-    br = (uint32_t)(t >> 32) & 1u;
-  }
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_subc(a.v[j], b.v[j], br, &br);
   const uint32_t mask = 0u - br;
-  uint32_t c = 0;
 #pragma unroll
-  for (int j = 0; j < kLimbs; ++j) {
-    uint64_t t = (uint64_t)d.v[j] + (F::P[j] & mask) + c;
-    d.v[j] = (uint32_t)t;
-    c = (uint32_t)(t >> 32);
-  }
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_addc(d.v[j], F::P[j] & mask, c, &c);
   return d;
 }
 
@@ -117,13 +100,9 @@ __host__ __device__ __forceinline__ Fe sub(const Fe& a, const Fe& b) {
 template <class F>
 __host__ __device__ __forceinline__ Fe reduce_once(const uint32_t t[kLimbs]) {
   Fe r, d;
-  uint32_t br = 0;
+  unsigned int br = 0;
 #pragma unroll
-  for (int j = 0; j < kLimbs; ++j) {
-    uint64_t s = (uint64_t)t[j] - F::P[j] - br;
-    d.v[j] = (uint32_t)s;
-    br = (uint32_t)(s >> 32) & 1u;
-  }
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_subc(t[j], F::P[j], br, &br);
 #pragma unroll
   for (int j = 0; j < kLimbs; ++j) r.v[j] = br ? t[j] : d.v[j];
   return r;
