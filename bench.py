@@ -8,7 +8,8 @@ elements per second over those seven transforms: 7 * 2^24 / step time.
 
 Also reported: the single forward NTT at 2^24 (elements/s); the roofline of
 the dominant kernel (the radix-256 pass kernel, timed per launch with HIP
-events on the stream it runs on); and the CPU oracle timed on a bounded
+events on the stream it runs on); batched versus per-launch jobs/s for 64
+uneven forward NTTs over both fields; and the CPU oracle timed on a bounded
 sample on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
@@ -70,12 +71,72 @@ def cpu_baseline(x_host) -> dict:
             "sample": f"one forward NTT at n=2^24 (BLS12-381 Fr) with the C oracle, {dt:.2f} s wall"}
 
 
+def batch_leg(dev, reps: int = 20) -> dict:
+    """64 forward NTTs (log2 n uniform in [10, 18], 48 BLS12-381 + 16 BN254):
+    jobs/s for one launch sequence per NTT versus one persistent launch."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_2509_22684_amd import Batch, Plan
+    from paper_2509_22684_amd.autotune import tuned_opts
+
+    jobs = si.batch_jobs()
+    plans = {}
+    bufs = []
+    for jb in jobs:
+        key = (jb.field, jb.log2n)
+        if key not in plans:
+            plans[key] = Plan(jb.field, jb.log2n, **tuned_opts(jb.field, jb.log2n, batchable=True))
+        x = si.uniform_field_vector(jb.field, 1 << jb.log2n, jb.seed)
+        bufs.append(torch.from_numpy(x.view(np.int32)).to(dev))
+    job_plans = [plans[(j.field, j.log2n)] for j in jobs]
+    works = [p.workspace(b) for p, b in zip(job_plans, bufs)]
+    stream = torch.cuda.current_stream(dev)
+
+    def per_launch():
+        for p, b, w in zip(job_plans, bufs, works):
+            p.forward(b, out=b)
+
+    batch = Batch(job_plans, bufs)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_per = timed(per_launch)
+    t_graph = timed(batch.launch)
+    t_eager = timed(batch.launch_eager)
+    status = batch.status()
+    elems = sum(1 << j.log2n for j in jobs)
+    launches = sum(p.passes for p in job_plans)
+    return {
+        "workload": "64 forward NTTs, log2 n uniform in [10,18], 48 BLS12-381 Fr + 16 BN254 Fr, seed 4",
+        "elements": elems,
+        "per_launch": {"ms": t_per, "jobs_per_s": len(jobs) / (t_per * 1e-3), "kernel_launches": launches},
+        "batched_graph": {"ms": t_graph, "jobs_per_s": len(jobs) / (t_graph * 1e-3), "items": batch.items,
+                          "workgroups": batch.grid},
+        "batched_direct": {"ms": t_eager, "jobs_per_s": len(jobs) / (t_eager * 1e-3)},
+        "batched_over_per_launch": t_per / t_graph,
+        "status": status,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -178,6 +239,9 @@ def main() -> int:
         "forward_ntt_2e24": {"ms_median": fwd_med, "elements_per_s": n / (fwd_med * 1e-3), "passes": npass},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        print("[bench] batched vs per-launch (64 jobs)", file=sys.stderr, flush=True)
+        result["batched"] = batch_leg(dev)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(host[0])

@@ -5,10 +5,10 @@
  * What the calls compute (ZKProphet, arXiv 2509.22684):
  *   - The NTT maps a vector a = [a_0 .. a_{n-1}] of field elements to A with
  *     A_i = sum_j a_j w^(i j), w a primitive n-th root of unity; the inverse
- *     transform (INTT) undoes it (Section II-C, "Number-Theoretic Transform").
+ *     transform (INTT) undoes it (Section II-B, "Number-Theoretic Transform").
  *   - The Groth16 prover derives the quotient polynomial h from the witness
  *     polynomials with forward and inverse NTTs interleaved with elementwise
- *     operations (Section II-A and Fig. 2); a proof runs seven NTTs
+ *     operations (Section II and Fig. 3); a proof runs seven NTTs
  *     (Section IV-A).
  *
  * Conventions fixed by this library where the paper leaves a choice open:
@@ -66,10 +66,12 @@ typedef enum {
 
 /* Plan options.  Zero in any field selects the tuned default. */
 typedef struct {
-  uint32_t twiddle_mode; /* 0 default, 1 precomputed tables in HBM */
-  uint32_t log2_radix;   /* radix of the in-register butterflies: 0 default, 1 (radix-2), 2, 3 */
-  uint32_t log2_tile;    /* elements per workgroup tile, log2: 0 default (11), 8..11 */
-  uint32_t flags;        /* ZK_FLAG_* */
+  uint32_t twiddle_mode;    /* 0 default; 1 one precomputed table per pass in HBM;
+                               2 two small tables and one extra multiplication per element */
+  uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (3), 1 (radix-2) or 3 */
+  uint32_t log2_tile;       /* elements per workgroup tile, log2: 0 default (11) or 11 */
+  uint32_t flags;           /* ZK_FLAG_* */
+  uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (8), 4..8 */
 } ntt_plan_opts;
 
 #define ZK_FLAG_VALIDATE 1u /* check that inputs are canonical (adds a device-to-host sync) */
@@ -87,7 +89,7 @@ size_t ntt_plan_device_bytes(const ntt_plan *p);
 /* Number of global passes (kernel launches) one transform takes. */
 int ntt_plan_passes(const ntt_plan *p);
 
-/* Forward NTT: out_i = sum_j in_j w^(i j)  (Section II-C).
+/* Forward NTT: out_i = sum_j in_j w^(i j)  (Section II-B).
  * d_in may equal d_out.  d_work: ntt_workspace_bytes(p) bytes, or NULL when
  * that is 0; it must not overlap d_in or d_out. */
 int ntt_forward(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
@@ -106,7 +108,7 @@ int ntt_coset_inverse(const ntt_plan *p, const void *d_in, void *d_out, void *d_
 /* Bytes of device workspace quotient_poly needs. */
 size_t quotient_workspace_bytes(const ntt_plan *p);
 
-/* Groth16 quotient chain (Section II-A, Fig. 2; seven NTTs, Section IV-A).
+/* Groth16 quotient chain (Section II, Fig. 3; seven NTTs, Section IV-A).
  * A, B, C are evaluations on <w> (natural order).  With a, b, c their
  * interpolating polynomials, computes on the coset g<w>
  *   E_i = (a(g w^i) b(g w^i) - c(g w^i)) / (g^n - 1)
@@ -116,6 +118,87 @@ size_t quotient_workspace_bytes(const ntt_plan *p);
  * A, B, C are not modified; H must not overlap them or d_work. */
 int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_H,
                   void *d_work, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent forward NTTs of uneven sizes and either field in
+ * one persistent launch.  GPU NTTs run as short, bursty kernels with launch
+ * shapes that fit some sizes badly (Section IV-A; Section V-A asks for autotuning of such parameters); a
+ * batch turns every job's passes into one pass-major work list of tiles that
+ * a grid of persistent workgroups drains, each tile computed exactly as in
+ * the stand-alone transform (so results are byte-identical to ntt_forward).
+ *
+ * Jobs need n >= 2^10 and the default radix-8 schedule with passes of
+ * 2^5..2^8 points (ZK_EUNSUPPORTED otherwise); each job transforms its buffer
+ * in place.  The batch binds the plans, buffers and workspace it was created
+ * with: they must stay valid until ntt_batch_destroy.  Launches of one batch
+ * must not overlap (they share the batch's queue counters).
+ * ------------------------------------------------------------------------ */
+typedef struct ntt_batch ntt_batch;
+
+/* Bytes of device workspace for a batch of these plans (ping-pong buffers of
+ * the multi-pass jobs). */
+size_t ntt_batch_workspace_bytes(const ntt_plan *const *plans, int njobs);
+
+/* Build the device work list for jobs k < njobs (forward NTT of d_bufs[k] in
+ * place with plans[k]) and capture its launch (a counter-reset kernel and the
+ * persistent kernel) into a HIP graph.  Synchronous. */
+int ntt_batch_create(ntt_batch **out, const ntt_plan *const *plans, void *const *d_bufs, int njobs,
+                     void *d_work);
+
+/* General batches: each job is one transform of any kind, or the pointwise
+ * step of the quotient chain.  Transform jobs follow the buffer rules of the
+ * single calls (in may equal out; work: ntt_workspace_bytes(plan) bytes of
+ * its own, distinct from in/out and from every other job's work).  Jobs run
+ * concurrently: no job may write a buffer another job of the same batch
+ * reads or writes. */
+typedef enum {
+  ZK_OP_FORWARD = 0,
+  ZK_OP_INVERSE = 1,
+  ZK_OP_COSET_FORWARD = 2,
+  ZK_OP_COSET_INVERSE = 3,
+  ZK_OP_INVERSE_TO_COSET = 4,     /* INTT then coefficient j times g^j: a coset NTT's input */
+  ZK_OP_QUOTIENT_POINTWISE = 5    /* out_i = (in_i in2_i - in3_i) / (g^n - 1); out may equal in3 */
+} zk_op;
+
+typedef struct {
+  const ntt_plan *plan; /* field and size (pointwise: n and g) */
+  int32_t op;           /* zk_op */
+  int32_t reserved;
+  const void *in;
+  const void *in2;      /* pointwise only */
+  const void *in3;      /* pointwise only */
+  void *out;
+  void *work;           /* transform workspace, or NULL when the plan needs none */
+} ntt_batch_job;
+
+#define ZK_BATCH_GRAPH 1 /* capture the launch into a HIP graph (ntt_batch_launch) */
+
+int ntt_batch_create_jobs(ntt_batch **out, const ntt_batch_job *jobs, int njobs, int flags);
+
+/* Replay the batch's graph on `stream`: one persistent launch runs all jobs. */
+int ntt_batch_launch(const ntt_batch *b, void *stream);
+
+/* The same two kernels launched directly on `stream`, without the graph. */
+int ntt_batch_launch_eager(const ntt_batch *b, void *stream);
+
+/* After the stream of the last launch has been synchronised: ZK_OK, or
+ * ZK_EDEVICE if a dependency wait exceeded its poll limit (the kernel then
+ * stops early and the outputs are invalid). */
+int ntt_batch_status(const ntt_batch *b);
+
+/* Poll limit of one dependency wait (default 2^22).  0 makes every
+ * dependency wait fail at once (a test hook for the error path).  Synchronous. */
+int ntt_batch_set_spin_limit(ntt_batch *b, uint32_t polls);
+
+/* Work items (tiles) in the batch and persistent workgroups per launch. */
+int ntt_batch_items(const ntt_batch *b);
+int ntt_batch_grid(const ntt_batch *b);
+
+void ntt_batch_destroy(ntt_batch *b);
+
+/* One-shot: build, launch without a graph, synchronise `stream`, check the
+ * status and free the batch. */
+int ntt_batch_forward(const ntt_plan *const *plans, void *const *d_bufs, int njobs, void *d_work, void *stream);
 
 /* Measurement helper: run one transform (kind 0 forward, 1 inverse, 2 coset
  * forward, 3 coset inverse; same buffer rules as the calls above) with a HIP

@@ -8,10 +8,10 @@
  * unity, coset powers, inverses, Montgomery factors) from the modulus and the
  * generator.
  *
- * What it computes (paper, Section II-C): the NTT maps a = [a_0 .. a_{n-1}]
+ * What it computes (paper, Section II-B): the NTT maps a = [a_0 .. a_{n-1}]
  * to A with A_i = sum_j a_j w^(i j), w a primitive n-th root of unity,
  * computed with the radix-2 Cooley-Tukey butterfly, n/2 butterflies in each
- * of log2(n) stages (Fig. 3b).  The quotient chain (Section II-A, Fig. 2;
+ * of log2(n) stages (Fig. 4(b)).  The quotient chain (Section II, Fig. 3;
  * seven NTTs per proof, Section IV-A) interleaves forward and inverse
  * transforms with elementwise products.
  *

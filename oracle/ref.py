@@ -2,12 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Notation follows the paper's background on the NTT (Section II-C): a vector
+Notation follows the paper's background on the NTT (Section II-B): a vector
 a = [a_0 .. a_{n-1}] of field elements maps to A with
 A_i = sum_j a_j * w^(i*j), w a primitive n-th root of unity; the fast
 algorithm is radix-2 Cooley-Tukey with n/2 butterflies per stage over
-log2(n) stages (Fig. 3b).  The Groth16 prover computes the quotient h with
-forward and inverse NTTs and elementwise products (Section II-A, Fig. 2;
+log2(n) stages (Fig. 4(b)).  The Groth16 prover computes the quotient h with
+forward and inverse NTTs and elementwise products (Section II, Fig. 3;
 seven NTTs, Section IV-A).
 
 Readings where the paper is silent (each listed in the design doc):
@@ -81,7 +81,7 @@ def _log2(n: int) -> int:
 # Plain definitions (quadratic).
 
 def dft(F: Field, a, w=None):
-    """A_i = sum_j a_j w^(i j) (Section II-C), straight from the definition."""
+    """A_i = sum_j a_j w^(i j) (Section II-B), straight from the definition."""
     n = len(a)
     p = F.p
     if w is None:
@@ -115,7 +115,7 @@ def horner(F: Field, coeffs, x: int) -> int:
 
 
 # --------------------------------------------------------------------------
-# Radix-2 Cooley-Tukey (Section II-C, Fig. 3b).
+# Radix-2 Cooley-Tukey (Section II-B, Fig. 4(b)).
 
 def bit_reverse(a):
     n = len(a)
@@ -158,7 +158,7 @@ def ntt_radix2(F: Field, a, w=None):
 
 
 def ntt(F: Field, a):
-    """Forward NTT of plain values (Section II-C)."""
+    """Forward NTT of plain values (Section II-B)."""
     return ntt_radix2(F, a)
 
 
@@ -194,7 +194,7 @@ def coset_intt(F: Field, A):
 
 
 def quotient(F: Field, A, B, C):
-    """Groth16 quotient chain (Section II-A; seven NTTs, Section IV-A).
+    """Groth16 quotient chain (Section II, Fig. 3; seven NTTs, Section IV-A).
 
     Inputs are evaluations on <w>; the output is the coefficient vector of
     h = (a b - c) / Z_H computed on the coset, where Z_H = g^n - 1.

@@ -9,6 +9,16 @@ binding raises.
 """
 from ._lib import (  # noqa: F401
     FIELDS,
+    Batch,
+    ntt_batch_create,
+    ntt_batch_create_jobs,
+    ntt_batch_destroy,
+    ntt_batch_forward,
+    ntt_batch_launch,
+    ntt_batch_launch_eager,
+    ntt_batch_set_spin_limit,
+    ntt_batch_status,
+    ntt_batch_workspace_bytes,
     Plan,
     ZkError,
     lib,

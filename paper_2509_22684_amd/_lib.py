@@ -27,8 +27,18 @@ class ZkError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("twiddle_mode", ctypes.c_uint32), ("log2_radix", ctypes.c_uint32),
-                ("log2_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("log2_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("log2_pass_radix", ctypes.c_uint32)]
 
+
+class _BatchJob(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("op", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("in_", ctypes.c_void_p), ("in2", ctypes.c_void_p), ("in3", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+OPS = {"forward": 0, "inverse": 1, "coset_forward": 2, "coset_inverse": 3, "inverse_to_coset": 4,
+       "quotient_pointwise": 5}
+ZK_BATCH_GRAPH = 1
 
 _lib = None
 
@@ -57,6 +67,25 @@ def lib() -> ctypes.CDLL:
         L.ntt_profile_passes.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float),
                                          ctypes.c_int]
         L.ntt_profile_passes.restype = ctypes.c_int
+        pp = ctypes.POINTER(vp)
+        L.ntt_batch_workspace_bytes.argtypes = [pp, ctypes.c_int]
+        L.ntt_batch_workspace_bytes.restype = sz
+        L.ntt_batch_create.argtypes = [pp, pp, pp, ctypes.c_int, vp]
+        L.ntt_batch_create.restype = ctypes.c_int
+        for name in ("ntt_batch_launch", "ntt_batch_launch_eager"):
+            getattr(L, name).argtypes = [vp, vp]
+            getattr(L, name).restype = ctypes.c_int
+        for name in ("ntt_batch_status", "ntt_batch_items", "ntt_batch_grid"):
+            getattr(L, name).argtypes = [vp]
+            getattr(L, name).restype = ctypes.c_int
+        L.ntt_batch_set_spin_limit.argtypes = [vp, ctypes.c_uint32]
+        L.ntt_batch_set_spin_limit.restype = ctypes.c_int
+        L.ntt_batch_destroy.argtypes = [vp]
+        L.ntt_batch_destroy.restype = None
+        L.ntt_batch_create_jobs.argtypes = [pp, ctypes.POINTER(_BatchJob), ctypes.c_int, ctypes.c_int]
+        L.ntt_batch_create_jobs.restype = ctypes.c_int
+        L.ntt_batch_forward.argtypes = [pp, pp, ctypes.c_int, vp, vp]
+        L.ntt_batch_forward.restype = ctypes.c_int
         L.zk_last_error.argtypes = []
         L.zk_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -99,9 +128,9 @@ def _field_id(field) -> int:
 # C ABI, one function per entry point
 
 def ntt_plan_create(field, log2n: int, twiddle_mode: int = 0, log2_radix: int = 0, log2_tile: int = 0,
-                    flags: int = 0) -> int:
+                    flags: int = 0, log2_pass_radix: int = 0) -> int:
     h = ctypes.c_void_p()
-    opts = _Opts(twiddle_mode, log2_radix, log2_tile, flags)
+    opts = _Opts(twiddle_mode, log2_radix, log2_tile, flags, log2_pass_radix)
     _check(lib().ntt_plan_create(ctypes.byref(h), _field_id(field), log2n, ctypes.byref(opts)), "ntt_plan_create")
     return h.value
 
@@ -168,11 +197,13 @@ class Plan:
     """A plan for n = 2^log2n transforms over `field` on the current device."""
 
     def __init__(self, field: str, log2n: int, twiddle_mode: int = 0, log2_radix: int = 0, log2_tile: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, log2_pass_radix: int = 0):
         self.field = field
         self.log2n = log2n
         self.n = 1 << log2n
-        self.handle = ntt_plan_create(field, log2n, twiddle_mode, log2_radix, log2_tile, flags)
+        self.opts = dict(twiddle_mode=twiddle_mode, log2_radix=log2_radix, log2_tile=log2_tile, flags=flags,
+                         log2_pass_radix=log2_pass_radix)
+        self.handle = ntt_plan_create(field, log2n, twiddle_mode, log2_radix, log2_tile, flags, log2_pass_radix)
         self._work = None
         self._qwork = None
 
@@ -238,3 +269,125 @@ class Plan:
             self._qwork = self._buf(nb, A)
         quotient_poly(self.handle, A, B, C, H, self._qwork, stream)
         return H
+
+
+# ---------------------------------------------------------------------------
+# Batches
+
+def _ptr_array(xs):
+    arr = (ctypes.c_void_p * max(1, len(xs)))()
+    for i, x in enumerate(xs):
+        arr[i] = _ptr(x)
+    return arr
+
+
+def _handles(plans):
+    return [p.handle if isinstance(p, Plan) else p for p in plans]
+
+
+def ntt_batch_workspace_bytes(plans) -> int:
+    hs = _handles(plans)
+    return lib().ntt_batch_workspace_bytes(_ptr_array(hs), len(hs))
+
+
+def ntt_batch_create(plans, d_bufs, d_work=None) -> int:
+    hs = _handles(plans)
+    if len(hs) != len(d_bufs):
+        raise ValueError("one buffer per plan")
+    h = ctypes.c_void_p()
+    _check(lib().ntt_batch_create(ctypes.byref(h), _ptr_array(hs), _ptr_array(d_bufs), len(hs), _ptr(d_work)),
+           "ntt_batch_create")
+    return h.value
+
+
+def ntt_batch_create_jobs(jobs, graph: bool = False) -> int:
+    """jobs: dicts with keys plan, op (name or zk_op), in, out and optionally
+    in2, in3 (pointwise) and work."""
+    arr = (_BatchJob * max(1, len(jobs)))()
+    for k, j in enumerate(jobs):
+        plan = j["plan"]
+        arr[k].plan = plan.handle if isinstance(plan, Plan) else plan
+        op = j["op"]
+        arr[k].op = OPS[op] if isinstance(op, str) else int(op)
+        arr[k].in_ = _ptr(j.get("in"))
+        arr[k].in2 = _ptr(j.get("in2"))
+        arr[k].in3 = _ptr(j.get("in3"))
+        arr[k].out = _ptr(j.get("out"))
+        arr[k].work = _ptr(j.get("work"))
+    h = ctypes.c_void_p()
+    _check(lib().ntt_batch_create_jobs(ctypes.byref(h), arr, len(jobs), ZK_BATCH_GRAPH if graph else 0),
+           "ntt_batch_create_jobs")
+    return h.value
+
+
+def ntt_batch_launch(batch: int, stream=None) -> None:
+    _check(lib().ntt_batch_launch(batch, _stream(stream)), "ntt_batch_launch")
+
+
+def ntt_batch_launch_eager(batch: int, stream=None) -> None:
+    _check(lib().ntt_batch_launch_eager(batch, _stream(stream)), "ntt_batch_launch_eager")
+
+
+def ntt_batch_status(batch: int) -> int:
+    return lib().ntt_batch_status(batch)
+
+
+def ntt_batch_set_spin_limit(batch: int, polls: int) -> None:
+    _check(lib().ntt_batch_set_spin_limit(batch, polls), "ntt_batch_set_spin_limit")
+
+
+def ntt_batch_destroy(batch: int) -> None:
+    lib().ntt_batch_destroy(batch)
+
+
+def ntt_batch_forward(plans, d_bufs, d_work=None, stream=None) -> None:
+    hs = _handles(plans)
+    _check(lib().ntt_batch_forward(_ptr_array(hs), _ptr_array(d_bufs), len(hs), _ptr(d_work),
+                                   _stream(stream, d_bufs[0] if d_bufs else None)), "ntt_batch_forward")
+
+
+class Batch:
+    """In-place forward NTTs of `bufs[k]` with `plans[k]`, one persistent launch
+    replayed from a HIP graph.  Keeps plans, buffers and workspace alive."""
+
+    def __init__(self, plans, bufs, work=None):
+        import torch
+
+        self.plans = list(plans)
+        self.bufs = list(bufs)
+        nb = ntt_batch_workspace_bytes(self.plans)
+        if work is None and nb:
+            work = torch.empty((nb + 31) // 32, 8, dtype=torch.int32, device=self.bufs[0].device)
+        self.work = work
+        self.handle = ntt_batch_create(self.plans, self.bufs, work)
+
+    @property
+    def items(self) -> int:
+        return lib().ntt_batch_items(self.handle)
+
+    @property
+    def grid(self) -> int:
+        return lib().ntt_batch_grid(self.handle)
+
+    def launch(self, stream=None) -> None:
+        ntt_batch_launch(self.handle, stream)
+
+    def launch_eager(self, stream=None) -> None:
+        ntt_batch_launch_eager(self.handle, stream)
+
+    def status(self) -> int:
+        return ntt_batch_status(self.handle)
+
+    def set_spin_limit(self, polls: int) -> None:
+        ntt_batch_set_spin_limit(self.handle, polls)
+
+    def close(self) -> None:
+        if self.handle:
+            ntt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,6 +19,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -27,6 +28,7 @@
 
 #include "../../include/zkntt.h"
 #include "field.hpp"
+#include "ntt_batch.hpp"
 #include "ntt_kernels.hpp"
 
 using zk::Fe;
@@ -69,6 +71,11 @@ struct ntt_plan {
   size_t device_bytes = 0;
   Fe n_inv{};        // 1/n, Montgomery
   Fe zinv{};         // 1/(g^n - 1), Montgomery
+  uint32_t twiddle_mode = 1;      // 1 table per pass, 2 two-level
+  uint32_t max_log_r = 8;         // stages per global pass
+  Fe* tw_lo = nullptr;            // two-level mode: w_n^k, k < 2^log_lo
+  Fe* tw_hi = nullptr;            //                 w_n^(k 2^log_lo)
+  uint32_t log_lo = 0;
   Fe* coset_fwd = nullptr;        // g^k
   Fe* coset_inv = nullptr;        // n^-1 g^-k
   Fe* inv_to_coset = nullptr;     // n^-1 g^k
@@ -148,15 +155,15 @@ void free_plan(ntt_plan* p) {
   delete p;
 }
 
-// Split log_n into passes of at most 8 stages each, larger radices first
-// (a single pass covers n <= 2^11 in one tile).
-std::vector<int> split_passes(uint32_t log_n) {
+// Split log_n into passes of at most max_log_r stages each, larger radices
+// first (a single pass covers n <= 2^11 in one tile).
+std::vector<int> split_passes(uint32_t log_n, uint32_t max_log_r) {
   std::vector<int> r;
   if (log_n <= 11) {
     r.push_back((int)log_n);
     return r;
   }
-  const int P = (int)((log_n + 7) / 8);
+  const int P = (int)((log_n + max_log_r - 1) / max_log_r);
   const int base = (int)log_n / P, extra = (int)log_n % P;
   for (int k = 0; k < P; ++k) r.push_back(base + (k < extra ? 1 : 0));
   return r;
@@ -177,7 +184,7 @@ int build_plan(ntt_plan* p) {
     p->zinv = zk::inv_mont<F>(zk::sub<F>(gn, one));
   }
 
-  std::vector<int> radices = split_passes(L);
+  std::vector<int> radices = split_passes(L, p->max_log_r);
   uint32_t log_ns = 0;
   Fe* tw_r_by_log[33] = {nullptr};
   for (size_t k = 0; k < radices.size(); ++k) {
@@ -185,8 +192,9 @@ int build_plan(ntt_plan* p) {
     d.log_r = radices[k];
     d.log_tile = (L <= 11) ? (int)L : 11;
     d.log_ns = log_ns;
-    if (k > 0 && (uint32_t)(d.log_tile - d.log_r) > log_ns)
-      return fail(ZK_EUNSUPPORTED, "pass schedule: tile wider than the previous passes' span");
+    if (!zk::pass_shape_supported(d.log_r, d.log_tile))
+      return fail(ZK_EUNSUPPORTED, "no pass kernel for a radix-2^" + std::to_string(d.log_r) +
+                                       " pass; choose a larger log2_pass_radix");
     if (!tw_r_by_log[d.log_r]) {
       const uint64_t R = 1ull << d.log_r;
       Fe* t = nullptr;
@@ -197,7 +205,7 @@ int build_plan(ntt_plan* p) {
       tw_r_by_log[d.log_r] = t;
     }
     d.tw_r = tw_r_by_log[d.log_r];
-    if (k > 0) {
+    if (k > 0 && p->twiddle_mode == 1) {
       const uint64_t ns = 1ull << log_ns, R = 1ull << d.log_r;
       const uint64_t count = ns * R;
       if (int rc = tb.alloc(&d.tw_pass, count)) return rc;
@@ -207,6 +215,18 @@ int build_plan(ntt_plan* p) {
     }
     p->passes.push_back(d);
     log_ns += (uint32_t)d.log_r;
+  }
+
+  if (radices.size() > 1 && p->twiddle_mode == 2) {
+    // two-level inter-pass twiddles: w_n^e = hi[e >> log_lo] * lo[e mod 2^log_lo]
+    p->log_lo = (L + 1) / 2;
+    const uint64_t nlo = 1ull << p->log_lo, nhi = 1ull << (L - p->log_lo);
+    if (int rc = tb.alloc(&p->tw_lo, nlo)) return rc;
+    if (int rc = tb.generate<F>(p->tw_lo, nlo, w_n, one, zk::kGenPowers, 1, 0)) return rc;
+    Fe w_step = w_n;
+    for (uint32_t i = 0; i < p->log_lo; ++i) w_step = zk::mul_portable<F>(w_step, w_step);
+    if (int rc = tb.alloc(&p->tw_hi, nhi)) return rc;
+    if (int rc = tb.generate<F>(p->tw_hi, nhi, w_step, one, zk::kGenPowers, 1, 0)) return rc;
   }
 
   // Coset tables.
@@ -253,6 +273,49 @@ int validate_input(ntt_plan* p, const void* x, hipStream_t s) {
   return ZK_OK;
 }
 
+// Arguments of pass k of a transform of `kind`: pass 0 reads `in`, the last
+// pass writes `out`, and the passes in between alternate between the
+// workspace and `out` (pass k writes work when k is even).  With an odd
+// number of passes the last one reads and writes `out` in place, which is
+// safe because the last pass writes exactly the elements each tile reads.
+zk::PassArgs make_pass_args(const ntt_plan* p, Kind kind, size_t k, const void* in, void* out, void* work) {
+  const size_t P = p->passes.size();
+  const PassDesc& d = p->passes[k];
+  zk::PassArgs a{};
+  a.in = static_cast<const Fe*>(k == 0 ? in : (k % 2 == 1 ? work : out));
+  a.out = static_cast<Fe*>(k + 1 == P ? out : (k % 2 == 0 ? work : out));
+  a.tw_pass = d.tw_pass;
+  a.tw_r = d.tw_r;
+  if (k > 0 && !d.tw_pass) {
+    a.tw_lo = p->tw_lo;
+    a.tw_hi = p->tw_hi;
+    a.log_lo = p->log_lo;
+  }
+  a.log_n = p->log_n;
+  a.log_ns = d.log_ns;
+  a.flags = 0;
+  if (k == 0) {
+    if (kind == kInverse || kind == kCosetInverse || kind == kInverseToCoset) a.flags |= zk::kPassReverseIn;
+    if (kind == kCosetForward) {
+      a.flags |= zk::kPassPreTable;
+      a.pre_table = p->coset_fwd;
+    }
+  }
+  if (k + 1 == P) {
+    if (kind == kInverse) {
+      a.flags |= zk::kPassPostConst;
+      a.post_const = p->n_inv;
+    } else if (kind == kCosetInverse) {
+      a.flags |= zk::kPassPostTable;
+      a.post_table = p->coset_inv;
+    } else if (kind == kInverseToCoset) {
+      a.flags |= zk::kPassPostTable;
+      a.post_table = p->inv_to_coset;
+    }
+  }
+  return a;
+}
+
 // events: optional array of P + 1 events recorded before each pass and
 // after the last one on stream s.
 int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, hipStream_t s,
@@ -264,33 +327,7 @@ int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void*
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     const PassDesc& d = p->passes[k];
-    zk::PassArgs a{};
-    a.in = static_cast<const Fe*>(k == 0 ? in : (k % 2 == 1 ? work : out));
-    a.out = static_cast<Fe*>(k + 1 == P ? out : (k % 2 == 0 ? work : out));
-    a.tw_pass = d.tw_pass;
-    a.tw_r = d.tw_r;
-    a.log_n = p->log_n;
-    a.log_ns = d.log_ns;
-    a.flags = 0;
-    if (k == 0) {
-      if (kind == kInverse || kind == kCosetInverse || kind == kInverseToCoset) a.flags |= zk::kPassReverseIn;
-      if (kind == kCosetForward) {
-        a.flags |= zk::kPassPreTable;
-        a.pre_table = p->coset_fwd;
-      }
-    }
-    if (k + 1 == P) {
-      if (kind == kInverse) {
-        a.flags |= zk::kPassPostConst;
-        a.post_const = p->n_inv;
-      } else if (kind == kCosetInverse) {
-        a.flags |= zk::kPassPostTable;
-        a.post_table = p->coset_inv;
-      } else if (kind == kInverseToCoset) {
-        a.flags |= zk::kPassPostTable;
-        a.post_table = p->inv_to_coset;
-      }
-    }
+    const zk::PassArgs a = make_pass_args(p, kind, k, in, out, work);
     hipError_t e = zk::launch_pass(p->field, d.log_r, d.log_tile, p->log_e, a, s);
     if (e != hipSuccess) return hip_fail(e, "NTT pass launch");
   }
@@ -336,7 +373,9 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
                                      std::to_string(adicity));
   ntt_plan_opts o{};
   if (opts) o = *opts;
-  if (o.twiddle_mode > 1) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0 or 1");
+  if (o.twiddle_mode > 2) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0, 1 or 2");
+  if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 8))
+    return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..8");
   if (!(o.log2_radix == 0 || o.log2_radix == 1 || o.log2_radix == 3))
     return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1 or 3");
   if (!(o.log2_tile == 0 || o.log2_tile == 11)) return fail(ZK_EUNSUPPORTED, "log2_tile must be 0 or 11");
@@ -349,6 +388,8 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->n = 1ull << log2n;
   p->log_e = o.log2_radix ? (int)o.log2_radix : 3;
   p->flags = o.flags;
+  p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
+  p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : 8;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -455,5 +496,266 @@ int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_ou
 }
 
 const char* zk_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+
+struct ntt_batch {
+  int device = 0;
+  uint32_t njobs = 0;
+  uint32_t nitems = 0;
+  uint32_t grid = 0;
+  void* d_mem = nullptr;
+  zk::BatchJob* d_jobs = nullptr;
+  zk::BatchItem* d_items = nullptr;
+  uint32_t* d_ctl = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr uint32_t kDefaultSpinLimit = 1u << 22;
+
+size_t batch_work_elems(const ntt_plan* const* plans, int njobs) {
+  size_t total = 0;
+  for (int k = 0; k < njobs; ++k)
+    if (plans[k]) total += workspace_elems(plans[k]);
+  return total;
+}
+
+void free_batch(ntt_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->d_mem) (void)hipFree(b->d_mem);
+  delete b;
+}
+
+bool op_to_kind(int op, Kind* k) {
+  switch (op) {
+    case ZK_OP_FORWARD: *k = kForward; return true;
+    case ZK_OP_INVERSE: *k = kInverse; return true;
+    case ZK_OP_COSET_FORWARD: *k = kCosetForward; return true;
+    case ZK_OP_COSET_INVERSE: *k = kCosetInverse; return true;
+    case ZK_OP_INVERSE_TO_COSET: *k = kInverseToCoset; return true;
+    default: return false;
+  }
+}
+
+int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool capture) {
+  if (!out) return fail(ZK_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (njobs < 0 || (njobs > 0 && !specs)) return fail(ZK_EINVAL, "bad job array");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+
+  std::vector<zk::BatchJob> jobs(njobs);
+  for (int k = 0; k < njobs; ++k) {
+    const ntt_batch_job& sp = specs[k];
+    const ntt_plan* p = sp.plan;
+    if (!p) return fail(ZK_EINVAL, "null plan in batch job " + std::to_string(k));
+    if (p->device != dev) return fail(ZK_EINVAL, "batch plans must live on the current device");
+    zk::BatchJob& J = jobs[k];
+    std::memset(&J, 0, sizeof J);
+    J.field = (uint32_t)p->field;
+    if (sp.op == ZK_OP_QUOTIENT_POINTWISE) {
+      if (!sp.in || !sp.in2 || !sp.in3 || !sp.out) return fail(ZK_EINVAL, "pointwise job needs in, in2, in3, out");
+      if (!aligned(sp.in) || !aligned(sp.in2) || !aligned(sp.in3) || !aligned(sp.out))
+        return fail(ZK_EINVAL, "batch buffers must be 256-byte aligned");
+      J.kind = zk::kJobPointwise;
+      J.npasses = 1;
+      J.pw.a = static_cast<const Fe*>(sp.in);
+      J.pw.b = static_cast<const Fe*>(sp.in2);
+      J.pw.c = static_cast<const Fe*>(sp.in3);
+      J.pw.out = static_cast<Fe*>(sp.out);
+      J.pw.zinv = p->zinv;
+      J.pw.n = p->n;
+      J.pass[0].tiles = (uint32_t)((p->n + (1u << zk::kPointwiseTileLog) - 1) >> zk::kPointwiseTileLog);
+      continue;
+    }
+    Kind kind;
+    if (!op_to_kind(sp.op, &kind)) return fail(ZK_EINVAL, "unknown batch op " + std::to_string(sp.op));
+    if (!sp.in || !sp.out || !aligned(sp.in) || !aligned(sp.out))
+      return fail(ZK_EINVAL, "batch buffers must be non-null and 256-byte aligned");
+    if (p->log_e != 3) return fail(ZK_EUNSUPPORTED, "batched launches use the radix-8 schedule");
+    if (p->passes.size() > (size_t)zk::kMaxBatchPasses) return fail(ZK_EUNSUPPORTED, "too many passes for a batch");
+    for (const PassDesc& d : p->passes)
+      if (!zk::batch_shape_supported(d.log_r, d.log_tile))
+        return fail(ZK_EUNSUPPORTED, "batched launches need n >= 2^10 and passes of 2^5..2^8 points");
+    if (workspace_elems(p)) {
+      if (!sp.work || !aligned(sp.work)) return fail(ZK_EINVAL, "batch job needs an aligned workspace");
+      if (sp.work == sp.in || sp.work == sp.out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
+    }
+    J.kind = zk::kJobTransform;
+    J.npasses = (uint32_t)p->passes.size();
+    for (size_t q = 0; q < p->passes.size(); ++q) {
+      J.pass[q].args = make_pass_args(p, kind, q, sp.in, sp.out, sp.work);
+      J.pass[q].log_r = p->passes[q].log_r;
+      J.pass[q].log_tile = p->passes[q].log_tile;
+      J.pass[q].tiles = (uint32_t)(p->n >> p->passes[q].log_tile);
+    }
+  }
+  // Work list: pass-major, larger jobs first within a pass.
+  std::vector<int> order(njobs);
+  for (int k = 0; k < njobs; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return specs[a].plan->log_n > specs[b].plan->log_n; });
+  std::vector<zk::BatchItem> items;
+  for (int q = 0; q < zk::kMaxBatchPasses; ++q)
+    for (int k : order)
+      if ((uint32_t)q < jobs[k].npasses)
+        for (uint32_t t = 0; t < jobs[k].pass[q].tiles; ++t) items.push_back(zk::BatchItem{(uint32_t)k, (uint32_t)q, t, 0});
+
+  ntt_batch* b = new (std::nothrow) ntt_batch();
+  if (!b) return fail(ZK_ENOMEM, "host allocation failed");
+  b->device = dev;
+  b->njobs = (uint32_t)njobs;
+  b->nitems = (uint32_t)items.size();
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * zk::batch_workgroups_per_cu());
+  const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
+  const size_t items_bytes = ((sizeof(zk::BatchItem) * items.size() + 255) / 256) * 256;
+  const size_t ctl_words = zk::kCtlDone + (size_t)njobs * zk::kMaxBatchPasses;
+  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + ctl_words * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "hipMalloc(batch)");
+  }
+  char* base = static_cast<char*>(b->d_mem);
+  b->d_jobs = reinterpret_cast<zk::BatchJob*>(base);
+  b->d_items = reinterpret_cast<zk::BatchItem*>(base + jobs_bytes);
+  b->d_ctl = reinterpret_cast<uint32_t*>(base + jobs_bytes + items_bytes);
+  std::vector<uint32_t> ctl(ctl_words, 0);
+  ctl[zk::kCtlSpinLimit] = kDefaultSpinLimit;
+  if (!jobs.empty()) e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(zk::BatchJob) * jobs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(b->d_items, items.data(), sizeof(zk::BatchItem) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_ctl, ctl.data(), ctl_words * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "hipMemcpy(batch descriptors)");
+  }
+  if (capture) {
+    // One graph: the counter reset kernel and the persistent kernel.
+    e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->d_ctl, b->njobs, b->grid, b->capture_stream);
+      e = hipStreamEndCapture(b->capture_stream, &b->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e, "batch graph capture");
+    }
+  }
+  *out = b;
+  return ZK_OK;
+}
+
+// Forward NTTs in place: job k transforms d_bufs[k] with its own slice of
+// the workspace.
+int forward_specs(std::vector<ntt_batch_job>* specs, const ntt_plan* const* plans, void* const* d_bufs, int njobs,
+                  void* d_work) {
+  if (njobs < 0 || (njobs > 0 && (!plans || !d_bufs))) return fail(ZK_EINVAL, "bad job arrays");
+  const size_t need = njobs > 0 ? batch_work_elems(plans, njobs) : 0;
+  if (need && (!d_work || !aligned(d_work))) return fail(ZK_EINVAL, "batch needs an aligned workspace");
+  Fe* work = static_cast<Fe*>(d_work);
+  specs->resize(njobs);
+  for (int k = 0; k < njobs; ++k) {
+    ntt_batch_job& sp = (*specs)[k];
+    std::memset(&sp, 0, sizeof sp);
+    sp.plan = plans[k];
+    sp.op = ZK_OP_FORWARD;
+    sp.in = d_bufs[k];
+    sp.out = d_bufs[k];
+    if (plans[k] && workspace_elems(plans[k])) {
+      sp.work = work;
+      work += workspace_elems(plans[k]);
+    }
+  }
+  return ZK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ntt_batch_workspace_bytes(const ntt_plan* const* plans, int njobs) {
+  return (plans && njobs > 0) ? batch_work_elems(plans, njobs) * sizeof(Fe) : 0;
+}
+
+int ntt_batch_create(ntt_batch** out, const ntt_plan* const* plans, void* const* d_bufs, int njobs, void* d_work) {
+  std::vector<ntt_batch_job> specs;
+  if (int rc = forward_specs(&specs, plans, d_bufs, njobs, d_work)) return rc;
+  return batch_build(out, specs.data(), njobs, true);
+}
+
+int ntt_batch_create_jobs(ntt_batch** out, const ntt_batch_job* jobs, int njobs, int flags) {
+  if (flags & ~ZK_BATCH_GRAPH) return fail(ZK_EUNSUPPORTED, "unknown batch flag bits");
+  return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0);
+}
+
+int ntt_batch_launch(const ntt_batch* b, void* stream) {
+  if (!b) return fail(ZK_EINVAL, "null batch");
+  if (!b->exec) return fail(ZK_EINVAL, "batch was created without a graph; use ntt_batch_launch_eager");
+  hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "hipGraphLaunch(batch)");
+}
+
+int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
+  if (!b) return fail(ZK_EINVAL, "null batch");
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->d_ctl, b->njobs, b->grid,
+                                  static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
+}
+
+int ntt_batch_status(const ntt_batch* b) {
+  if (!b) return fail(ZK_EINVAL, "null batch");
+  uint32_t err = 0;
+  hipError_t e = hipMemcpy(&err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "batch status readback");
+  if (err) return fail(ZK_EDEVICE, "a batched dependency wait exceeded its poll limit; outputs are invalid");
+  return ZK_OK;
+}
+
+int ntt_batch_set_spin_limit(ntt_batch* b, uint32_t polls) {
+  if (!b) return fail(ZK_EINVAL, "null batch");
+  hipError_t e = hipMemcpy(b->d_ctl + zk::kCtlSpinLimit, &polls, sizeof polls, hipMemcpyHostToDevice);
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "batch spin limit");
+}
+
+int ntt_batch_items(const ntt_batch* b) { return b ? (int)b->nitems : 0; }
+
+int ntt_batch_grid(const ntt_batch* b) { return b ? (int)b->grid : 0; }
+
+void ntt_batch_destroy(ntt_batch* b) { free_batch(b); }
+
+int ntt_batch_forward(const ntt_plan* const* plans, void* const* d_bufs, int njobs, void* d_work, void* stream) {
+  std::vector<ntt_batch_job> specs;
+  if (int rc = forward_specs(&specs, plans, d_bufs, njobs, d_work)) return rc;
+  ntt_batch* b = nullptr;
+  int rc = batch_build(&b, specs.data(), njobs, false);
+  if (rc) return rc;
+  rc = ntt_batch_launch_eager(b, stream);
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    rc = e == hipSuccess ? ntt_batch_status(b) : hip_fail(e, "batch synchronise");
+  }
+  free_batch(b);
+  return rc;
+}
 
 }  // extern "C"

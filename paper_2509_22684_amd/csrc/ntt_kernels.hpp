@@ -20,18 +20,34 @@ enum PassFlags : uint32_t {
 // column j by the inter-pass twiddle w_{Ns R}^(r (j mod Ns)), runs an R-point
 // DFT, and writes output r of column j to (j / Ns) Ns R + (j mod Ns) + r Ns,
 // where Ns = 2^log_ns is the product of the radices of the earlier passes.
+//
+// Inter-pass twiddles come either from tw_pass, a table [r][j mod Ns] read in
+// the same order as the data, or (tw_pass null, tw_hi non-null) from two
+// small tables: w_n^e = tw_hi[e >> log_lo] * tw_lo[e mod 2^log_lo] with
+// e = (n / (Ns R)) r (j mod Ns), one extra multiplication per element.
 struct PassArgs {
   const Fe* in;
   Fe* out;
   const Fe* tw_pass;     // [r * Ns + (j mod Ns)], null on the first pass
   const Fe* tw_r;        // w_R^k for k < R
+  const Fe* tw_lo;       // w_n^k, k < 2^log_lo (two-level mode)
+  const Fe* tw_hi;       // w_n^(k 2^log_lo)    (two-level mode)
   const Fe* pre_table;   // see kPassPreTable
   const Fe* post_table;  // see kPassPostTable
   Fe post_const;         // see kPassPostConst
   uint32_t log_n;
   uint32_t log_ns;
   uint32_t flags;
+  uint32_t log_lo;
 };
+
+// Shapes the pass kernels are instantiated for: tiles of 2^11 elements with
+// 2^3 .. 2^8 points per column, or one tile holding a whole transform of up
+// to 2^11 points.
+inline bool pass_shape_supported(int log_r, int log_tile) {
+  if (log_tile == 11) return (log_r >= 3 && log_r <= 8) || log_r == 11;
+  return log_tile == log_r && log_r >= 0 && log_r <= 10;
+}
 
 // Launch one pass; log_r + log_j = log_tile.  Returns hipSuccess or the
 // launch error.

@@ -1,6 +1,6 @@
 // NTT pass kernels for gfx950.
 //
-// The transform follows the paper's description of GPU NTTs (Section II-C):
+// The transform follows the paper's description of GPU NTTs (Section II-B):
 // radix-2 Cooley-Tukey butterflies, with a block of threads performing a
 // radix-2^k sub-transform through on-chip shared memory and several stages
 // processed per batch.  Here each workgroup runs one radix-R "pass" of a
@@ -122,7 +122,7 @@ struct PassShape {
 // their outputs (i / Nsr) Nsr Er + (i mod Nsr) + s Nsr back to LDS.
 template <class F, int LOG_R, int LOG_TILE, int LOG_E, int RHO, int N>
 __device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __restrict__ tw_r, uint32_t c,
-                                           uint32_t q) {
+                                           uint32_t q, bool writer) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
   constexpr int LOG_NSR = RHO * S::LE;
   constexpr int LR = S::round_log(RHO);
@@ -158,30 +158,32 @@ __device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __rest
 
   if constexpr (!LAST) {
     if constexpr (RHO > 0) __syncthreads();  // every thread has read this round's inputs
-    sfor<S::EL>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      const uint32_t i = q + (e / ER) * S::SLOT_STRIDE;
-      const uint32_t o = (i >> LOG_NSR) * (NSR * ER) + (i & (NSR - 1)) + (e % ER) * NSR;
-      lds[lds_slot(o * S::J + c)] = v[e];
-    });
+    if (writer) {
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        const uint32_t i = q + (e / ER) * S::SLOT_STRIDE;
+        const uint32_t o = (i >> LOG_NSR) * (NSR * ER) + (i & (NSR - 1)) + (e % ER) * NSR;
+        lds[lds_slot(o * S::J + c)] = v[e];
+      });
+    }
     __syncthreads();
-    tile_round<F, LOG_R, LOG_TILE, LOG_E, RHO + 1>(v, lds, tw_r, c, q);
+    tile_round<F, LOG_R, LOG_TILE, LOG_E, RHO + 1>(v, lds, tw_r, c, q, writer);
   }
 }
 
+// One tile of one pass: J columns x R points.  `t` is the thread's index
+// within the tile (t < THREADS); threads with `writer` false shadow thread t
+// (same loads and arithmetic) but store nothing, so a workgroup wider than
+// the tile still reaches every barrier.  `lds` holds LDS_SLOTS elements.
 template <class F, int LOG_R, int LOG_TILE, int LOG_E>
-__global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
-    ntt_pass_kernel(PassArgs a) {
+__device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* lds, uint32_t t, bool writer) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
-  __shared__ Fe lds[S::LDS_SLOTS];
-
-  const uint32_t t = threadIdx.x;
   const uint32_t c = t & (S::J - 1);  // column within the tile
   const uint32_t q = t >> S::LOG_J;   // thread index within the column
   const uint64_t n = 1ull << a.log_n;
   const uint64_t ns = 1ull << a.log_ns;
-  const uint64_t j = (uint64_t)blockIdx.x * S::J + c;  // global column, < n / R
-  const uint32_t log_stride = a.log_n - LOG_R;         // column stride n / R
+  const uint64_t j = tile * S::J + c;           // global column, < n / R
+  const uint32_t log_stride = a.log_n - LOG_R;  // column stride n / R
 
   // Round 0 reads its points r = i + s (R / Er0) straight from global memory.
   constexpr int ER0 = 1 << S::round_log(0);
@@ -204,9 +206,19 @@ __global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
       constexpr int e = decltype(e_)::value;
       v[e] = mul<F>(v[e], load_fe(a.tw_pass, (point0(e) << a.log_ns) + (j & (ns - 1))));
     });
+  } else if (a.tw_hi) {  // the same twiddle from the two-level tables
+    const uint64_t jm = j & (ns - 1);
+    const uint32_t log_mult = a.log_n - a.log_ns - LOG_R;
+    const uint64_t lo_mask = (1ull << a.log_lo) - 1;
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint64_t ex = (point0(e) * jm) << log_mult;
+      const Fe w = mul<F>(load_fe(a.tw_hi, ex >> a.log_lo), load_fe(a.tw_lo, ex & lo_mask));
+      v[e] = mul<F>(v[e], w);
+    });
   }
 
-  if constexpr (S::ROUNDS > 0) tile_round<F, LOG_R, LOG_TILE, LOG_E, 0>(v, lds, a.tw_r, c, q);
+  if constexpr (S::ROUNDS > 0) tile_round<F, LOG_R, LOG_TILE, LOG_E, 0>(v, lds, a.tw_r, c, q, writer);
 
   // The last round leaves output r_out = i + s (R / Er) of column j in
   // v[g Er + s]; it goes to (j / Ns) Ns R + (j mod Ns) + r_out Ns.
@@ -228,10 +240,20 @@ __global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
       v[e] = mul<F>(v[e], a.post_const);
     });
   }
-  sfor<S::EL>([&](auto e_) {
-    constexpr int e = decltype(e_)::value;
-    store_fe(a.out, out_index(e), v[e]);
-  });
+  if (writer) {
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      store_fe(a.out, out_index(e), v[e]);
+    });
+  }
+}
+
+template <class F, int LOG_R, int LOG_TILE, int LOG_E>
+__global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
+    ntt_pass_kernel(PassArgs a) {
+  using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
+  __shared__ Fe lds[S::LDS_SLOTS];
+  pass_tile<F, LOG_R, LOG_TILE, LOG_E>(a, blockIdx.x, lds, threadIdx.x, true);
 }
 
 }  // namespace detail
@@ -248,12 +270,15 @@ hipError_t launch_one(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Multi-pass tiles of 2^11 elements with radix 2^5 .. 2^8 per pass, and
-// single-pass transforms of up to 2^11 points held in one tile.
+// Multi-pass tiles of 2^11 elements with radix 2^3 .. 2^8 per pass, and
+// single-pass transforms of up to 2^11 points held in one tile.  Keep in step
+// with pass_shape_supported().
 template <class F, int LOG_E>
 hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_t s) {
   if (log_tile == 11) {
     switch (log_r) {
+      case 3: return launch_one<F, 3, 11, LOG_E>(a, s);
+      case 4: return launch_one<F, 4, 11, LOG_E>(a, s);
       case 5: return launch_one<F, 5, 11, LOG_E>(a, s);
       case 6: return launch_one<F, 6, 11, LOG_E>(a, s);
       case 7: return launch_one<F, 7, 11, LOG_E>(a, s);

@@ -1,0 +1,153 @@
+"""GPU parity of the persistent batched launch.
+
+Workload: 64 independent forward NTTs, log2 n uniform in [10, 18], 48 on
+BLS12-381 Fr and 16 on BN254 Fr (seeded_inputs.batch_jobs).  Every job's
+output must equal the oracle and its stand-alone ntt_forward result byte for
+byte, for the graph replay (several replays with other GPU work between
+them), the direct launch and the one-shot call.  The error path of the
+bounded dependency wait is forced from the host.
+"""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import coracle
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c4(cuda):
+    from paper_2509_22684_amd import Plan
+
+    jobs = si.batch_jobs()
+    plans = {}
+    inputs, want = [], []
+    for jb in jobs:
+        key = (jb.field, jb.log2n)
+        if key not in plans:
+            plans[key] = Plan(jb.field, jb.log2n)
+        x = si.uniform_field_vector(jb.field, 1 << jb.log2n, jb.seed)
+        inputs.append(x)
+        want.append(coracle.transform(jb.field, "forward", x))
+    return jobs, plans, inputs, want
+
+
+def _fresh_bufs(inputs, cuda):
+    return [to_dev(x, cuda) for x in inputs]
+
+
+def _reset(bufs, inputs):
+    import torch
+
+    for b, x in zip(bufs, inputs):
+        b.copy_(torch.from_numpy(x.view(np.int32)))
+
+
+def _check_all(bufs, want, what):
+    for k, (b, w) in enumerate(zip(bufs, want)):
+        got = to_host(b)
+        assert np.array_equal(got, w), f"{what}: job {k} differs"
+
+
+def test_workload_shape(c4):
+    jobs = c4[0]
+    assert len(jobs) == 64
+    assert sum(j.field == "bn254_fr" for j in jobs) == 16
+    assert all(10 <= j.log2n <= 18 for j in jobs)
+
+
+def test_batch_graph_matches_oracle_and_per_launch(c4, cuda):
+    import torch
+
+    from paper_2509_22684_amd import Batch
+
+    jobs, plans, inputs, want = c4
+    job_plans = [plans[(j.field, j.log2n)] for j in jobs]
+    bufs = _fresh_bufs(inputs, cuda)
+    batch = Batch(job_plans, bufs)
+    assert batch.items > 64 and batch.grid > 0
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, "graph launch")
+    # per-launch reference path, byte-identical
+    per = _fresh_bufs(inputs, cuda)
+    for p, b in zip(job_plans, per):
+        p.forward(b, out=b)
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(bufs, per)):
+        assert torch.equal(a, b), f"job {k}: batch and per-launch differ"
+    # replays with unrelated GPU work in between
+    for rep in range(3):
+        _reset(bufs, inputs)
+        junk = torch.randint(0, 1 << 30, (1 << 20, 8), dtype=torch.int32, device=cuda)
+        job_plans[0].forward(junk[: job_plans[0].n].contiguous())
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        assert batch.status() == 0
+        _check_all(bufs, want, f"graph replay {rep}")
+    # direct launch without the graph
+    _reset(bufs, inputs)
+    batch.launch_eager()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, "eager launch")
+    batch.close()
+
+
+def test_batch_one_shot(c4, cuda):
+    import torch
+
+    from paper_2509_22684_amd import ntt_batch_forward, ntt_batch_workspace_bytes
+
+    jobs, plans, inputs, want = c4
+    job_plans = [plans[(j.field, j.log2n)] for j in jobs[:20]]
+    bufs = _fresh_bufs(inputs[:20], cuda)
+    nb = ntt_batch_workspace_bytes(job_plans)
+    work = torch.empty((nb + 31) // 32, 8, dtype=torch.int32, device=cuda)
+    ntt_batch_forward(job_plans, bufs, work)
+    _check_all(bufs, want[:20], "one-shot")
+
+
+def test_forced_dependency_timeout_reports_error_and_recovers(c4, cuda):
+    """Spin limit 0 makes every dependency wait fail at once: the kernel exits
+    early and the status says so; with the limit restored the same batch
+    computes correct results again."""
+    import torch
+
+    from paper_2509_22684_amd import Batch
+
+    jobs, plans, inputs, want = c4
+    sel = [k for k, j in enumerate(jobs) if j.log2n >= 14][:8]
+    job_plans = [plans[(jobs[k].field, jobs[k].log2n)] for k in sel]
+    ins = [inputs[k] for k in sel]
+    bufs = _fresh_bufs(ins, cuda)
+    batch = Batch(job_plans, bufs)
+    batch.set_spin_limit(0)
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == -4
+    batch.set_spin_limit(1 << 22)
+    _reset(bufs, ins)
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, [want[k] for k in sel], "after recovery")
+
+
+def test_batch_rejects_unsupported_jobs(cuda):
+    from paper_2509_22684_amd import Batch, Plan, ZkError
+
+    small = Plan("bls12_381_fr", 9)
+    buf = to_dev(si.uniform_field_vector("bls12_381_fr", 1 << 9, 1), cuda)
+    with pytest.raises(ZkError) as e:
+        Batch([small], [buf])
+    assert e.value.code == -2
+    r2 = Plan("bls12_381_fr", 12, log2_radix=1)
+    buf = to_dev(si.uniform_field_vector("bls12_381_fr", 1 << 12, 1), cuda)
+    with pytest.raises(ZkError) as e:
+        Batch([r2], [buf])
+    assert e.value.code == -2

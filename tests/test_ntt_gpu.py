@@ -154,3 +154,18 @@ def test_validate_flag_rejects_noncanonical(cuda):
     with pytest.raises(ZkError) as e:
         plan.forward(to_dev(bad, cuda))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("opts", [dict(twiddle_mode=2), dict(log2_pass_radix=6), dict(log2_pass_radix=4),
+                                  dict(log2_pass_radix=7, twiddle_mode=2), dict(log2_pass_radix=5),
+                                  dict(log2_pass_radix=4, twiddle_mode=2)])
+@pytest.mark.parametrize("log2n", [12, 17, 20])
+def test_schedules_are_byte_identical(cuda, opts, log2n):
+    """Every schedule the autotuner may pick (pass fusion depth, twiddle
+    source) gives the oracle's bytes for all four transforms."""
+    field = "bn254_fr" if log2n == 17 else "bls12_381_fr"
+    x = si.uniform_field_vector(field, 1 << log2n, si.stream_seed(9, log2n, 0))
+    dx = to_dev(x, cuda)
+    plan = _plan(field, log2n, **opts)
+    for kind in KINDS:
+        _check(to_host(_run(plan, kind, dx)), coracle.transform(field, kind, x), f"{opts} {kind} 2^{log2n}")
