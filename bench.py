@@ -130,6 +130,41 @@ def batch_leg(dev, reps: int = 20) -> dict:
     }
 
 
+def serve_leg(dev, njobs: int = 128, rate_per_s: float = 300.0) -> dict:
+    """Quotient jobs on BLS12-381 Fr arriving as a Poisson process (seed 5,
+    log2 n uniform in [14, 22]) served with continuous batching under a
+    200 GB HBM budget.  Each job's A, B, C come from a device-resident pool
+    of one seeded vector triple per size, copied into the job's own buffers
+    on admission; latency runs from arrival to H ready on the device."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_2509_22684_amd.serve import GpuExecutor, QuotientServer, Request, summarize
+
+    specs = si.serve_jobs(master=5, njobs=njobs, rate_per_s=rate_per_s)
+    pool = {}
+    for L in sorted({s.log2n for s in specs}):
+        pool[L] = tuple(torch.from_numpy(si.uniform_field_vector(FIELD, 1 << L, si.stream_seed(5, 1000 + L, v))
+                                         .view(np.int32)).to(dev) for v in range(3))
+    reqs = [Request(s.job_id, s.log2n, s.arrival_s, pool[s.log2n]) for s in specs]
+    ex = GpuExecutor(FIELD, dev, keep_results=False)
+    for L in pool:  # plans (twiddle tables) stay resident across jobs
+        ex.plan(L)
+    # warm up the kernels once
+    QuotientServer(ex, 200 << 30).run(reqs[:4], realtime=False)
+    ex.ticks = ex.tick_jobs = 0
+    srv = QuotientServer(ex, budget_bytes=200 << 30)
+    res = srv.run(reqs, realtime=True)
+    out = summarize(res)
+    out.update({"workload": f"{njobs} quotient jobs, Poisson arrivals at {rate_per_s}/s (seed 5), "
+                            "log2 n uniform in [14,22], BLS12-381 Fr, 200 GB budget",
+                "rate_per_s": rate_per_s, "ticks": ex.ticks,
+                "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "max_inflight": srv.max_inflight,
+                "peak_bytes": srv.peak_bytes})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +172,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--only", choices=["forward", "copy"], default=None,
+                    help="for counter runs: only run --steps forward NTTs at 2^24, or --steps plain device "
+                         "copies of one 512 MiB vector (the traffic calibration kernel), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -154,6 +193,24 @@ def main() -> int:
 
     def to_dev(a):
         return torch.from_numpy(np.ascontiguousarray(a).view(np.int32).copy()).to(dev)
+
+    if args.only == "copy":
+        src = torch.randint(-(1 << 31), (1 << 31) - 1, (n, 8), dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] {args.steps} copies of {n * 32} bytes done", file=sys.stderr, flush=True)
+        return 0
+    if args.only == "forward":
+        x = to_dev(si.uniform_field_vector(FIELD, n, si.stream_seed(3, 0, 0)))
+        plan = Plan(FIELD, LOG2N)
+        out = torch.empty_like(x)
+        for _ in range(args.steps):
+            plan.forward(x, out)
+        torch.cuda.synchronize()
+        print(f"[bench] {args.steps} forward NTTs at 2^{LOG2N} done", file=sys.stderr, flush=True)
+        return 0
 
     print(f"[bench] generating inputs n=2^{LOG2N}", file=sys.stderr, flush=True)
     host = [si.uniform_field_vector(FIELD, n, si.stream_seed(3, 0, v)) for v in range(3)]
@@ -206,7 +263,7 @@ def main() -> int:
     traffic = traffic_from_profile(khash)
     roofline = {
         "bound": "alu",
-        "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE=11, LOG_E=3>",
+        "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE=11, LOG_E={plan.opts['log2_radix'] or 2}>",
         "achieved": achieved / 1e12,
         "peak": PEAK_MAD_PER_S / 1e12,
         "unit": "T MAD/s",
@@ -242,6 +299,9 @@ def main() -> int:
     if not args.no_batch:
         print("[bench] batched vs per-launch (64 jobs)", file=sys.stderr, flush=True)
         result["batched"] = batch_leg(dev)
+    if not args.no_serve:
+        print("[bench] serving (Poisson quotient jobs)", file=sys.stderr, flush=True)
+        result["serving"] = serve_leg(dev)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(host[0])

@@ -68,7 +68,7 @@ typedef enum {
 typedef struct {
   uint32_t twiddle_mode;    /* 0 default; 1 one precomputed table per pass in HBM;
                                2 two small tables and one extra multiplication per element */
-  uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (3), 1 (radix-2) or 3 */
+  uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (2), 1 (radix-2), 2 or 3 */
   uint32_t log2_tile;       /* elements per workgroup tile, log2: 0 default (11) or 11 */
   uint32_t flags;           /* ZK_FLAG_* */
   uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (8), 4..8 */
@@ -127,10 +127,11 @@ int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const voi
  * a grid of persistent workgroups drains, each tile computed exactly as in
  * the stand-alone transform (so results are byte-identical to ntt_forward).
  *
- * Jobs need n >= 2^10 and the default radix-8 schedule with passes of
- * 2^5..2^8 points (ZK_EUNSUPPORTED otherwise); each job transforms its buffer
- * in place.  The batch binds the plans, buffers and workspace it was created
- * with: they must stay valid until ntt_batch_destroy.  Launches of one batch
+ * Jobs need n >= 4 and at most 4 global passes (ZK_EUNSUPPORTED otherwise);
+ * the batch computes every tile with its own radix-4 register schedule,
+ * whatever register radix the plan uses (the bytes are the same).
+ * The batch binds the plans, buffers and workspace it was created with: they
+ * must stay valid until ntt_batch_destroy.  Launches of one batch
  * must not overlap (they share the batch's queue counters).
  * ------------------------------------------------------------------------ */
 typedef struct ntt_batch ntt_batch;

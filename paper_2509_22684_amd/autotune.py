@@ -30,18 +30,15 @@ def db_path() -> str:
 
 def candidates(log2n: int, batchable: bool = False) -> list[dict]:
     """Schedules to try at this size.  batchable restricts to those the
-    persistent batch kernel runs (radix-8 registers, passes of 2^5..2^8)."""
+    persistent batch kernel runs (passes of 2^5..2^8 points)."""
+    radices = (2,) if batchable else (1, 2, 3)
     if log2n <= 11:
-        c = [dict()]
-        if not batchable:
-            c.append(dict(log2_radix=1))
-        return c
+        return [dict(log2_radix=e) for e in radices]
     out = []
-    for pr in (6, 7, 8):
-        for tm in (1, 2):
-            out.append(dict(log2_pass_radix=pr, twiddle_mode=tm))
-    if not batchable:
-        out.append(dict(log2_radix=1))
+    for e in radices:
+        for pr in (6, 7, 8):
+            for tm in (1, 2):
+                out.append(dict(log2_radix=e, log2_pass_radix=pr, twiddle_mode=tm))
     return out
 
 

@@ -63,7 +63,7 @@ struct ntt_plan {
   int field = 0;
   uint32_t log_n = 0;
   uint64_t n = 0;
-  int log_e = 3;
+  int log_e = 2;
   uint32_t flags = 0;
   int device = 0;
   std::vector<PassDesc> passes;
@@ -376,8 +376,7 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   if (o.twiddle_mode > 2) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0, 1 or 2");
   if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 8))
     return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..8");
-  if (!(o.log2_radix == 0 || o.log2_radix == 1 || o.log2_radix == 3))
-    return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1 or 3");
+  if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
   if (!(o.log2_tile == 0 || o.log2_tile == 11)) return fail(ZK_EUNSUPPORTED, "log2_tile must be 0 or 11");
   if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
 
@@ -386,7 +385,7 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->field = field;
   p->log_n = log2n;
   p->n = 1ull << log2n;
-  p->log_e = o.log2_radix ? (int)o.log2_radix : 3;
+  p->log_e = o.log2_radix ? (int)o.log2_radix : 2;
   p->flags = o.flags;
   p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
   p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : 8;
@@ -506,6 +505,7 @@ struct ntt_batch {
   int device = 0;
   uint32_t njobs = 0;
   uint32_t nitems = 0;
+  uint32_t nfirst = 0;  // items of BLS12-381 jobs, listed first
   uint32_t grid = 0;
   void* d_mem = nullptr;
   zk::BatchJob* d_jobs = nullptr;
@@ -583,11 +583,10 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     if (!op_to_kind(sp.op, &kind)) return fail(ZK_EINVAL, "unknown batch op " + std::to_string(sp.op));
     if (!sp.in || !sp.out || !aligned(sp.in) || !aligned(sp.out))
       return fail(ZK_EINVAL, "batch buffers must be non-null and 256-byte aligned");
-    if (p->log_e != 3) return fail(ZK_EUNSUPPORTED, "batched launches use the radix-8 schedule");
     if (p->passes.size() > (size_t)zk::kMaxBatchPasses) return fail(ZK_EUNSUPPORTED, "too many passes for a batch");
     for (const PassDesc& d : p->passes)
       if (!zk::batch_shape_supported(d.log_r, d.log_tile))
-        return fail(ZK_EUNSUPPORTED, "batched launches need n >= 2^10 and passes of 2^5..2^8 points");
+        return fail(ZK_EUNSUPPORTED, "batched launches need n >= 4 (passes of at least 4 points)");
     if (workspace_elems(p)) {
       if (!sp.work || !aligned(sp.work)) return fail(ZK_EINVAL, "batch job needs an aligned workspace");
       if (sp.work == sp.in || sp.work == sp.out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
@@ -601,22 +600,30 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       J.pass[q].tiles = (uint32_t)(p->n >> p->passes[q].log_tile);
     }
   }
-  // Work list: pass-major, larger jobs first within a pass.
+  // Work list: the BLS12-381 jobs' items, then the BN254 jobs' items (the
+  // kernel drains the two groups in two loops, one per field); each group
+  // pass-major with larger jobs first within a pass.
   std::vector<int> order(njobs);
   for (int k = 0; k < njobs; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return specs[a].plan->log_n > specs[b].plan->log_n; });
   std::vector<zk::BatchItem> items;
-  for (int q = 0; q < zk::kMaxBatchPasses; ++q)
-    for (int k : order)
-      if ((uint32_t)q < jobs[k].npasses)
-        for (uint32_t t = 0; t < jobs[k].pass[q].tiles; ++t) items.push_back(zk::BatchItem{(uint32_t)k, (uint32_t)q, t, 0});
+  uint32_t nfirst = 0;
+  for (uint32_t field : {(uint32_t)zk::Bls12_381Fr::ID, (uint32_t)zk::Bn254Fr::ID}) {
+    for (int q = 0; q < zk::kMaxBatchPasses; ++q)
+      for (int k : order)
+        if (jobs[k].field == field && (uint32_t)q < jobs[k].npasses)
+          for (uint32_t t = 0; t < jobs[k].pass[q].tiles; ++t)
+            items.push_back(zk::BatchItem{(uint32_t)k, (uint32_t)q, t, 0});
+    if (field == (uint32_t)zk::Bls12_381Fr::ID) nfirst = (uint32_t)items.size();
+  }
 
   ntt_batch* b = new (std::nothrow) ntt_batch();
   if (!b) return fail(ZK_ENOMEM, "host allocation failed");
   b->device = dev;
   b->njobs = (uint32_t)njobs;
   b->nitems = (uint32_t)items.size();
+  b->nfirst = nfirst;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
@@ -651,7 +658,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->d_ctl, b->njobs, b->grid, b->capture_stream);
+      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->nfirst, b->d_ctl, b->njobs, b->grid,
+                                        b->capture_stream);
       e = hipStreamEndCapture(b->capture_stream, &b->graph);
       if (le != hipSuccess) e = le;
     }
@@ -717,7 +725,7 @@ int ntt_batch_launch(const ntt_batch* b, void* stream) {
 
 int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->d_ctl, b->njobs, b->grid,
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->nfirst, b->d_ctl, b->njobs, b->grid,
                                   static_cast<hipStream_t>(stream));
   return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
 }

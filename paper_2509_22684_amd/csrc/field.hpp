@@ -158,6 +158,24 @@ __device__ __forceinline__ uint64_t mad_co_vs(uint32_t a, uint32_t b, uint64_t c
   asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "s"(b), "v"(c));
   return r;
 }
+// Ordered (volatile) forms for mul_k: the compiler keeps volatile asm in
+// source order, which is how the K chains stay interleaved.
+__device__ __forceinline__ uint64_t mad_co_vv_ord(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint64_t mad_co_vs_ord(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t add_carry_ord(uint32_t x, uint64_t ci) {
+  uint32_t r;
+  uint64_t unused;
+  asm volatile("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(unused) : "v"(x), "s"(ci));
+  return r;
+}
 // x + (carry bit of this lane)
 __device__ __forceinline__ uint32_t add_carry(uint32_t x, uint64_t ci) {
   uint32_t r;
@@ -214,11 +232,73 @@ __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
 #undef ZK_TERM_P
   return reduce_once<F>(r);  // the result is below 2p
 }
+// K independent Montgomery products r[k] = a[k] b[k], computed column by
+// column in lock step.  Each column of one product is a serial chain
+// (v_mad_u64_u32 -> v_mad_u64_u32 through the accumulator, v_addc through
+// the counter); emitting the K chains' instructions alternately gives every
+// instruction K-1 independent instructions of distance from the one it
+// waits for, which hides the issue latency the single chain exposes and
+// removes the carry-hazard wait states.  The result of each product is
+// identical to mul().
+template <class F, int K>
+__device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
+  uint32_t m[K][kLimbs], t[K][kLimbs];
+  uint64_t acc[K], co[K];
+  uint32_t hi[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = 0;
+    hi[k] = 0;
+  }
+#define ZK_TERMS(X, Y, MADFN)                                        \
+  {                                                                  \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) acc[k] = MADFN(X, Y, acc[k], co[k]); \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) hi[k] = add_carry_ord(hi[k], co[k]);  \
+  }
+#pragma unroll
+  for (int i = 0; i < kLimbs; ++i) {
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      ZK_TERMS(a[k].v[j], b[k].v[i - j], mad_co_vv_ord);
+      ZK_TERMS(m[k][j], F::P[i - j], mad_co_vs_ord);
+    }
+    ZK_TERMS(a[k].v[i], b[k].v[0], mad_co_vv_ord);
+#pragma unroll
+    for (int k = 0; k < K; ++k) m[k][i] = (uint32_t)acc[k] * F::INV;
+    ZK_TERMS(m[k][i], F::P[0], mad_co_vs_ord);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
+      hi[k] = 0;
+    }
+  }
+#pragma unroll
+  for (int i = kLimbs; i < 2 * kLimbs; ++i) {
+#pragma unroll
+    for (int j = i - (kLimbs - 1); j < kLimbs; ++j) {
+      ZK_TERMS(a[k].v[j], b[k].v[i - j], mad_co_vv_ord);
+      ZK_TERMS(m[k][j], F::P[i - j], mad_co_vs_ord);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      t[k][i - kLimbs] = (uint32_t)acc[k];
+      acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
+      hi[k] = 0;
+    }
+  }
+#undef ZK_TERMS
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = reduce_once<F>(t[k]);
+}
 #else
 // Host compilation pass: device code is parsed but never emitted here.
 template <class F>
 __host__ __device__ inline Fe mul(const Fe& a, const Fe& b) {
   return mul_portable<F>(a, b);
+}
+template <class F, int K>
+__host__ __device__ inline void mul_k(Fe* r, const Fe* a, const Fe* b) {
+  for (int k = 0; k < K; ++k) r[k] = mul_portable<F>(a[k], b[k]);
 }
 #endif
 

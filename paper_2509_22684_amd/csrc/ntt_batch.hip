@@ -22,36 +22,184 @@
 namespace zk {
 namespace {
 
-constexpr int kBatchThreads = 256;
+// Tiles of 2^11 elements computed with the radix-4 register schedule: 512
+// threads of four elements each.
+constexpr int kBatchLogE = 2;
+constexpr int kBatchThreads = (1 << 11) >> kBatchLogE;
 constexpr int kBatchLdsSlots = (1 << 11) + (1 << 11) / 8;
+#ifndef ZK_DYN_GROUP
+#define ZK_DYN_GROUP 2
+#endif
+constexpr int kDynGroup = ZK_DYN_GROUP;
 
-__device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Control words are read with relaxed device-scope atomics; the one acquire
+// fence after a satisfied dependency wait and the one release fence before a
+// completion count are the only cache-maintenance points of an item.  (An
+// acquire load in the poll loop would invalidate caches on every poll.)
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Inlined (not a call) so that log_r and log_tile stay wave-uniform scalars
-// and every branch around the tile's barriers is a uniform scalar branch.
+// One tile of one pass with the pass shape taken at run time: J columns x R
+// points (R = 2^log_r, J R = 2^log_tile), four points per thread, radix-4
+// register rounds and, when log_r is odd, a final radix-2 round.  The
+// arithmetic is that of pass_tile with LOG_E = 2 step for step (same loads,
+// same twiddle exponents, same butterflies in the same order), so the bytes
+// equal those of the stand-alone kernels; only the index arithmetic is
+// computed at run time, so the persistent loop holds one tile body per field
+// and its register allocation is that of a single shape.  Threads t >=
+// 2^(log_tile - 2) shadow thread t mod 2^(log_tile - 2) and store nothing.
+// log_r and log_tile are wave-uniform; 2 <= log_r <= log_tile <= 11.
 template <class F>
-__device__ __forceinline__ void run_tile(const PassArgs& a, int log_r, int log_tile, uint32_t tile, Fe* lds) {
-  const uint32_t t = threadIdx.x;
-  if (log_tile == 11) {
-    switch (log_r) {
-      case 5: detail::pass_tile<F, 5, 11, 3>(a, tile, lds, t, true); return;
-      case 6: detail::pass_tile<F, 6, 11, 3>(a, tile, lds, t, true); return;
-      case 7: detail::pass_tile<F, 7, 11, 3>(a, tile, lds, t, true); return;
-      case 8: detail::pass_tile<F, 8, 11, 3>(a, tile, lds, t, true); return;
-      case 11: detail::pass_tile<F, 11, 11, 3>(a, tile, lds, t, true); return;
-      default: return;
+__device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_tile, uint32_t tile, Fe* lds) {
+  using detail::lds_slot;
+  using detail::load_fe;
+  using detail::sfor;
+  const int log_threads = log_tile - 2;
+  const bool writer = threadIdx.x < (1u << log_threads);
+  const uint32_t t = threadIdx.x & ((1u << log_threads) - 1);
+  const int log_j = log_tile - log_r;
+  const uint32_t J = 1u << log_j;
+  const uint32_t c = t & (J - 1);
+  const uint32_t q = t >> log_j;
+  const uint32_t R = 1u << log_r;
+  const uint32_t quarter = R >> 2;  // threads per column
+  const uint64_t n = 1ull << a.log_n;
+  const uint64_t ns = 1ull << a.log_ns;
+  const uint64_t j = (uint64_t)tile * J + c;
+  const uint32_t log_stride = a.log_n - log_r;
+
+  // round 0 is radix 4: thread q holds points q + e R/4
+  Fe v[4];
+  const bool rev = a.flags & kPassReverseIn;
+  sfor<4>([&](auto e_) {
+    constexpr int e = decltype(e_)::value;
+    const uint64_t idx = j + ((uint64_t)(q + e * quarter) << log_stride);
+    v[e] = load_fe(a.in, rev ? ((n - idx) & (n - 1)) : idx);
+  });
+  Fe w[4];
+  if (a.flags & kPassPreTable) {
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      w[e] = load_fe(a.pre_table, j + ((uint64_t)(q + e * quarter) << log_stride));
+    });
+    detail::mul_many<F, 4, kDynGroup>(v, w);
+  }
+  if (a.tw_pass) {
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      w[e] = load_fe(a.tw_pass, ((uint64_t)(q + e * quarter) << a.log_ns) + (j & (ns - 1)));
+    });
+    detail::mul_many<F, 4, kDynGroup>(v, w);
+  } else if (a.tw_hi) {
+    const uint64_t jm = j & (ns - 1);
+    const uint32_t log_mult = a.log_n - a.log_ns - log_r;
+    const uint64_t lo_mask = (1ull << a.log_lo) - 1;
+    Fe lo[4];
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint64_t ex = ((uint64_t)(q + e * quarter) * jm) << log_mult;
+      w[e] = load_fe(a.tw_hi, ex >> a.log_lo);
+      lo[e] = load_fe(a.tw_lo, ex & lo_mask);
+    });
+    detail::mul_many<F, 4, kDynGroup>(w, lo);
+    detail::mul_many<F, 4, kDynGroup>(v, w);
+  }
+
+  const int r4 = log_r >> 1;  // radix-4 rounds
+  const bool odd = log_r & 1;
+  for (int rho = 0; rho < r4; ++rho) {
+    const int log_nsr = 2 * rho;
+    const uint32_t nsr = 1u << log_nsr;
+    if (rho > 0) {
+      sfor<4>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        v[e] = lds[lds_slot((q + e * quarter) * J + c)];
+      });
+      // in-tile twiddles w_{4 Nsr}^(s (q mod Nsr)) for s = 1, 2, 3
+      const uint32_t im = q & (nsr - 1);
+      const int log_step = log_r - log_nsr - 2;  // R / (Nsr 4)
+      Fe ws[3];
+      sfor<3>([&](auto k_) {
+        constexpr int k = decltype(k_)::value;
+        ws[k] = a.tw_r[((k + 1) * im) << log_step];
+      });
+      detail::mul_many<F, 3, kDynGroup>(v + 1, ws);
+    }
+    Fe W[2];
+    W[0] = a.tw_r[0];
+    W[1] = a.tw_r[quarter];  // w_4
+    detail::dft_regs<F, 2, 0>(v, W);
+    const bool last = !odd && rho == r4 - 1;
+    if (!last) {
+      if (rho > 0) __syncthreads();
+      if (writer) {
+        sfor<4>([&](auto e_) {
+          constexpr int e = decltype(e_)::value;
+          const uint32_t o = ((q >> log_nsr) << (log_nsr + 2)) + (q & (nsr - 1)) + e * nsr;
+          lds[lds_slot(o * J + c)] = v[e];
+        });
+      }
+      __syncthreads();
     }
   }
-  if (log_tile == 10 && log_r == 10) {
-    // 128 threads cover the tile; the upper half shadows the lower half.
-    detail::pass_tile<F, 10, 10, 3>(a, tile, lds, t & 127u, t < 128u);
+  if (odd) {
+    // final radix-2 round: thread q owns slots i = q + g R/4 (g < 2), each
+    // taking points i and i + R/2
+    const int log_nsr = 2 * r4;
+    const uint32_t nsr = 1u << log_nsr;
+    const uint32_t half = R >> 1;
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint32_t i = q + (e >> 1) * quarter;
+      v[e] = lds[lds_slot((i + (e & 1) * half) * J + c)];
+    });
+    Fe ys[2], ws[2];
+    sfor<2>([&](auto g_) {
+      constexpr int g = decltype(g_)::value;
+      const uint32_t im = (q + g * quarter) & (nsr - 1);
+      ys[g] = v[2 * g + 1];
+      ws[g] = a.tw_r[im];  // w_{2 Nsr}^im = tw_r[im R / (2 Nsr)], and R = 2 Nsr here
+    });
+    detail::mul_many<F, 2, kDynGroup>(ys, ws);
+    v[1] = ys[0];
+    v[3] = ys[1];
+    Fe W[1];
+    W[0] = a.tw_r[0];
+    detail::dft_regs<F, 1, 0>(v, W);
+    detail::dft_regs<F, 1, 2>(v, W);
+  }
+
+  // output r_out of column j goes to (j / Ns) Ns R + (j mod Ns) + r_out Ns
+  const uint64_t base = ((j >> a.log_ns) << (a.log_ns + log_r)) + (j & (ns - 1));
+  auto out_index = [&](int e) -> uint64_t {
+    const uint32_t r_out = odd ? q + (e >> 1) * quarter + (e & 1) * (R >> 1) : q + e * quarter;
+    return base + ((uint64_t)r_out << a.log_ns);
+  };
+  if (a.flags & kPassPostTable) {
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      w[e] = load_fe(a.post_table, out_index(e));
+    });
+    detail::mul_many<F, 4, kDynGroup>(v, w);
+  }
+  if (a.flags & kPassPostConst) {
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      w[e] = a.post_const;
+    });
+    detail::mul_many<F, 4, kDynGroup>(v, w);
+  }
+  if (writer) {
+    sfor<4>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      detail::store_fe(a.out, out_index(e), v[e]);
+    });
   }
 }
 
-// Pointwise quotient step on one tile: 2^11 elements, 8 per thread, lanes on
-// consecutive elements.
+// Pointwise quotient step on one tile: 2^11 elements, lanes on consecutive
+// elements.
 template <class F>
 __device__ __forceinline__ void run_pointwise(const PointwiseArgs& pw, uint32_t tile) {
   const uint64_t base = ((uint64_t)tile << kPointwiseTileLog) + threadIdx.x;
@@ -65,34 +213,43 @@ __device__ __forceinline__ void run_pointwise(const PointwiseArgs& pw, uint32_t 
   }
 }
 
-__global__ void __launch_bounds__(kBatchThreads) ntt_batch_kernel(const BatchJob* __restrict__ jobs,
-                                                                 const BatchItem* __restrict__ items,
-                                                                 uint32_t nitems, uint32_t* ctl) {
-  __shared__ Fe lds[kBatchLdsSlots];
-  __shared__ uint32_t s_item;
-  __shared__ uint32_t s_abort;
-  uint32_t* head = ctl + kCtlHead;
-  uint32_t* error = ctl + kCtlError;
-  const uint32_t spin_limit = ctl[kCtlSpinLimit];
-  uint32_t* done = ctl + kCtlDone;
+// Shared state of the persistent loop.
+struct QueueCtl {
+  uint32_t* head;
+  uint32_t* error;
+  uint32_t* done;
+  uint32_t spin_limit;
+};
 
-  // Every loop exit and branch below depends only on values made
-  // wave-uniform with readfirstlane, so the loop stays a uniform loop and all
-  // threads reach each barrier together.  (Were the exits derived from plain
-  // LDS reads, the compiler could treat them as divergent and restructure the
-  // loop so that thread 0 finishes its queue work after the other threads
-  // have already passed the next barrier.)
-  for (;;) {
-    if (threadIdx.x == 0) {
-      s_item = atomicAdd(head, 1u);
-      s_abort = load_acquire(error);
-    }
-    __syncthreads();
-    const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
-    const uint32_t abort = __builtin_amdgcn_readfirstlane(s_abort);
-    __syncthreads();
-    if (abort != 0 || it >= nitems) break;
+constexpr uint32_t kStop = 0xffffffffu;
 
+// Pop the next item index for the whole workgroup, or kStop once the error
+// flag is set.  The value is made wave-uniform with readfirstlane, so every
+// loop exit below is a uniform branch and all threads reach each barrier
+// together.  (Were the exits derived from plain LDS reads, the compiler could
+// treat them as divergent and restructure the loop so that thread 0 finishes
+// its queue work after the other threads have passed the next barrier.)
+__device__ __forceinline__ uint32_t pop_item(const QueueCtl& q, uint32_t* s_item, uint32_t* s_abort) {
+  if (threadIdx.x == 0) {
+    *s_item = atomicAdd(q.head, 1u);
+    *s_abort = load_relaxed(q.error);
+  }
+  __syncthreads();
+  const uint32_t it = __builtin_amdgcn_readfirstlane(*s_item);
+  const uint32_t abort = __builtin_amdgcn_readfirstlane(*s_abort);
+  __syncthreads();
+  return abort != 0 ? kStop : it;
+}
+
+// Run popped items while they fall below `end` (all of them jobs on field
+// F); return the first popped index at or past `end`, or kStop.  Each field
+// has its own loop so that each loop body is register-allocated for one
+// field's arithmetic alone.
+template <class F>
+__device__ __forceinline__ uint32_t drain(uint32_t it, uint32_t end, const BatchJob* __restrict__ jobs,
+                                          const BatchItem* __restrict__ items, const QueueCtl& q, Fe* lds,
+                                          uint32_t* s_item, uint32_t* s_abort) {
+  while (it < end) {
     const uint32_t job_id = __builtin_amdgcn_readfirstlane(items[it].job);
     const uint32_t pass = __builtin_amdgcn_readfirstlane(items[it].pass);
     const uint32_t tile = __builtin_amdgcn_readfirstlane(items[it].tile);
@@ -100,46 +257,60 @@ __global__ void __launch_bounds__(kBatchThreads) ntt_batch_kernel(const BatchJob
     if (pass > 0) {
       if (threadIdx.x == 0) {
         const uint32_t need = job.pass[pass - 1].tiles;
-        const uint32_t* cnt = done + job_id * kMaxBatchPasses + (pass - 1);
-        if (spin_limit == 0) {
-          atomicOr(error, 1u);  // test hook: every dependency wait fails at once
+        const uint32_t* cnt = q.done + job_id * kMaxBatchPasses + (pass - 1);
+        if (q.spin_limit == 0) {
+          atomicOr(q.error, 1u);  // test hook: every dependency wait fails at once
         } else {
           uint32_t spins = 0;
-          while (load_acquire(cnt) < need) {
+          while (load_relaxed(cnt) < need) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins > spin_limit) {
-              atomicOr(error, 1u);
+            if (++spins > q.spin_limit) {
+              atomicOr(q.error, 1u);
               break;
             }
           }
         }
-        s_abort = load_acquire(error);
+        *s_abort = load_relaxed(q.error);
       }
       __syncthreads();
-      const uint32_t failed = __builtin_amdgcn_readfirstlane(s_abort);
-      if (failed != 0) break;
+      const uint32_t failed = __builtin_amdgcn_readfirstlane(*s_abort);
+      if (failed != 0) return kStop;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     const uint32_t kind = __builtin_amdgcn_readfirstlane(job.kind);
-    const uint32_t field = __builtin_amdgcn_readfirstlane(job.field);
     if (kind == kJobPointwise) {
-      if (field == Bls12_381Fr::ID) run_pointwise<Bls12_381Fr>(job.pw, tile);
-      else run_pointwise<Bn254Fr>(job.pw, tile);
+      run_pointwise<F>(job.pw, tile);
     } else {
       const BatchPass& bp = job.pass[pass];
       const int log_r = __builtin_amdgcn_readfirstlane(bp.log_r);
       const int log_tile = __builtin_amdgcn_readfirstlane(bp.log_tile);
-      if (field == Bls12_381Fr::ID) run_tile<Bls12_381Fr>(bp.args, log_r, log_tile, tile, lds);
-      else run_tile<Bn254Fr>(bp.args, log_r, log_tile, tile, lds);
+      tile_dyn<F>(bp.args, log_r, log_tile, tile, lds);
     }
 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this thread's stores are visible device-wide
     __syncthreads();                                     // ... for every thread of the tile
     if (threadIdx.x == 0) {
-      __hip_atomic_fetch_add(done + job_id * kMaxBatchPasses + pass, 1u, __ATOMIC_RELEASE,
+      __hip_atomic_fetch_add(q.done + job_id * kMaxBatchPasses + pass, 1u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
+    it = pop_item(q, s_item, s_abort);
   }
+  return it;
+}
+
+// Items [0, nfirst) are BLS12-381 Fr work, [nfirst, nitems) BN254 Fr work.
+// Items are popped in list order, so a workgroup leaves the first loop for
+// good once the queue passes nfirst.
+__global__ void __launch_bounds__(kBatchThreads, 4) ntt_batch_kernel(const BatchJob* __restrict__ jobs,
+                                                                 const BatchItem* __restrict__ items,
+                                                                 uint32_t nitems, uint32_t nfirst, uint32_t* ctl) {
+  __shared__ Fe lds[kBatchLdsSlots];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_abort;
+  const QueueCtl q{ctl + kCtlHead, ctl + kCtlError, ctl + kCtlDone, ctl[kCtlSpinLimit]};
+  uint32_t it = pop_item(q, &s_item, &s_abort);
+  it = drain<Bls12_381Fr>(it, nfirst, jobs, items, q, lds, &s_item, &s_abort);
+  drain<Bn254Fr>(it, nitems, jobs, items, q, lds, &s_item, &s_abort);
 }
 
 // Zero the queue head, the error flag and the completion counters (a kernel
@@ -156,21 +327,20 @@ __global__ void __launch_bounds__(256) ntt_batch_reset_kernel(uint32_t* ctl, uin
 }  // namespace
 
 bool batch_shape_supported(int log_r, int log_tile) {
-  if (log_tile == 11) return (log_r >= 5 && log_r <= 8) || log_r == 11;
-  return log_tile == 10 && log_r == 10;
+  return log_r >= 2 && log_r <= log_tile && log_tile <= 11 && (log_tile == 11 || log_r == log_tile);
 }
 
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t* ctl,
-                        uint32_t njobs, uint32_t grid, hipStream_t s) {
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t nfirst,
+                        uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s) {
   const uint32_t ndone = njobs * kMaxBatchPasses;
   hipLaunchKernelGGL(ntt_batch_reset_kernel, dim3((ndone + 255) / 256 + 1), dim3(256), 0, s, ctl, ndone);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nitems == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, nitems, ctl);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, nitems, nfirst, ctl);
   return hipGetLastError();
 }
 
-int batch_workgroups_per_cu() { return 1; }  // registers: one 256-thread workgroup per CU
+int batch_workgroups_per_cu() { return 2; }  // LDS: 72 KiB per workgroup of the 160 KiB per CU
 
 }  // namespace zk

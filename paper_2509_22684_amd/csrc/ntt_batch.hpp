@@ -58,8 +58,9 @@ bool batch_shape_supported(int log_r, int log_tile);
 int batch_workgroups_per_cu();
 
 // Reset the control words of njobs jobs, then launch `grid` persistent
-// workgroups over `nitems` items.
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t* ctl,
-                        uint32_t njobs, uint32_t grid, hipStream_t s);
+// workgroups over `nitems` items, of which items [0, nfirst) belong to
+// BLS12-381 Fr jobs and the rest to BN254 Fr jobs.
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t nfirst,
+                        uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s);
 
 }  // namespace zk

@@ -8,8 +8,10 @@
 namespace zk {
 
 hipError_t launch_pass_bls_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bls_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_bls_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_bn_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bn_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_bn_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 
 namespace {
@@ -64,9 +66,11 @@ inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + pe
 hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const PassArgs& a, hipStream_t s) {
   if (field == Bls12_381Fr::ID) {
     if (log_e == 3) return launch_pass_bls_e3(log_r, log_tile, a, s);
+    if (log_e == 2) return launch_pass_bls_e2(log_r, log_tile, a, s);
     if (log_e == 1) return launch_pass_bls_e1(log_r, log_tile, a, s);
   } else if (field == Bn254Fr::ID) {
     if (log_e == 3) return launch_pass_bn_e3(log_r, log_tile, a, s);
+    if (log_e == 2) return launch_pass_bn_e2(log_r, log_tile, a, s);
     if (log_e == 1) return launch_pass_bn_e1(log_r, log_tile, a, s);
   }
   return hipErrorInvalidValue;

@@ -10,10 +10,10 @@
 //     consecutive columns (J x 32 bytes per row) and coalesced stores, so no
 //     separate bit-reversal or shuffle pass exists and input and output are
 //     in natural order;
-//   * inside the tile, every thread keeps E = 8 elements in registers and
-//     runs radix-8 DIT butterflies on them; rounds of radix-8 are separated
-//     by one exchange through LDS (padded so 32-byte elements do not
-//     conflict on banks);
+//   * inside the tile, every thread keeps E = 2^LOG_E elements in registers
+//     (E = 4 by default, 2 or 8 by plan option) and runs radix-E DIT
+//     butterflies on them; rounds are separated by one exchange through LDS
+//     (padded so 32-byte elements do not conflict on banks);
 //   * the twiddles between passes come from a table laid out in the order
 //     the pass reads its data ([r][j mod Ns]), so they stream coalesced
 //     alongside it; in-tile twiddles come from a small w_R table.
@@ -66,11 +66,41 @@ __device__ __forceinline__ void sfor(Fn&& fn) {
   sfor_impl(fn, std::make_integer_sequence<int, N>{});
 }
 
+// Independent products run GROUP at a time, interleaved (mul_k).  More
+// products in flight hide more latency but hold more registers: with the
+// 128-VGPR budget of four waves per SIMD, threads holding eight elements
+// interleave two products, threads holding four interleave three (measured
+// fastest on MI355X against two and four, which spills), and threads holding
+// two interleave up to four.
+template <int EL>
+constexpr int mul_group() {
+  return EL >= 8 ? 2 : EL == 4 ? 3 : 4;
+}
+
+// x[k] = x[k] w[k] for k < N, in interleaved groups of GROUP products.
+template <class F, int N, int GROUP>
+__device__ __forceinline__ void mul_many(Fe* x, const Fe* w) {
+  constexpr int G = N / GROUP, REST = N % GROUP;
+  sfor<G>([&](auto g_) {
+    constexpr int g = decltype(g_)::value;
+    mul_k<F, GROUP>(x + GROUP * g, x + GROUP * g, w + GROUP * g);
+  });
+  if constexpr (REST == 1) {
+    // a lone product keeps the reorderable form, which the scheduler can
+    // overlap with surrounding loads and LDS traffic
+    x[GROUP * G] = mul<F>(x[GROUP * G], w[GROUP * G]);
+  } else if constexpr (REST > 1) {
+    mul_k<F, REST>(x + GROUP * G, x + GROUP * G, w + GROUP * G);
+  }
+}
+
 // In-register DFT of E = 2^LOGE points (natural order in and out) on
 // v[OFF .. OFF + E): bit-reversed renaming, then log2 E radix-2 DIT stages
 // with butterflies (x, y) -> (x + w y, x - w y).  W[k] = w_E^k for k < E/2.
+// The multiplications of one stage are independent and run interleaved.
 template <class F, int LOGE, int OFF, int N>
 __device__ __forceinline__ void dft_regs(Fe (&v)[N], const Fe* W) {
+  constexpr int GROUP = mul_group<N>();
   constexpr int E = 1 << LOGE;
   if constexpr (E > 1) {
     Fe a[E];
@@ -81,13 +111,35 @@ __device__ __forceinline__ void dft_regs(Fe (&v)[N], const Fe* W) {
     sfor<LOGE>([&](auto st_) {
       constexpr int st = decltype(st_)::value;
       constexpr int half = 1 << st;  // butterflies pair elements half apart
+      // butterfly u has twiddle index t = u mod half; t != 0 needs a product
+      constexpr int NM = (E / 2) - (E / 2) / half;
+      if constexpr (NM > 0) {
+        Fe ys[NM], ws[NM];
+        sfor<E / 2>([&](auto u_) {
+          constexpr int u = decltype(u_)::value;
+          constexpr int t = u & (half - 1);
+          constexpr int b = (u >> st) << (st + 1);
+          constexpr int k = u - (u / half) - 1;  // rank among the t != 0 butterflies
+          if constexpr (t != 0) {
+            ys[k] = a[b + t + half];
+            ws[k] = W[t << (LOGE - 1 - st)];
+          }
+        });
+        mul_many<F, NM, GROUP>(ys, ws);
+        sfor<E / 2>([&](auto u_) {
+          constexpr int u = decltype(u_)::value;
+          constexpr int t = u & (half - 1);
+          constexpr int b = (u >> st) << (st + 1);
+          constexpr int k = u - (u / half) - 1;
+          if constexpr (t != 0) a[b + t + half] = ys[k];
+        });
+      }
       sfor<E / 2>([&](auto u_) {
         constexpr int u = decltype(u_)::value;
         constexpr int t = u & (half - 1);
         constexpr int b = (u >> st) << (st + 1);
-        Fe y = a[b + t + half];
-        if constexpr (t != 0) y = mul<F>(y, W[t << (LOGE - 1 - st)]);
         const Fe x = a[b + t];
+        const Fe y = a[b + t + half];
         a[b + t] = add<F>(x, y);
         a[b + t + half] = sub<F>(x, y);
       });
@@ -110,6 +162,9 @@ struct PassShape {
   static constexpr int ROUNDS = LOG_R == 0 ? 0 : (LOG_R + LE - 1) / LE;
   static constexpr int LDS_SLOTS = ROUNDS > 1 ? (1 << LOG_TILE) + (1 << LOG_TILE) / 8 : 1;
   static constexpr int SLOT_STRIDE = R / EL;  // threads per column
+  // Waves per SIMD the register allocation aims for: two workgroups of this
+  // tile per CU (the LDS limit) need 2 * THREADS / 256 waves on each SIMD.
+  static constexpr int MIN_WAVES = THREADS >= 256 ? 2 * THREADS / 256 : 1;
   // log2 radix of in-tile round rho: full LE except possibly the last
   static constexpr int round_log(int rho) { return imin(LE, LOG_R - rho * LE); }
 };
@@ -137,13 +192,24 @@ __device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __rest
       const uint32_t idx = i + (e % ER) * (S::R / ER);
       v[e] = lds[lds_slot(idx * S::J + c)];
     });
+    // in-tile twiddles of the points with s = e mod Er != 0, interleaved
+    constexpr int NM = S::EL - S::EL / ER;
+    Fe ys[NM], ws[NM];
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
       constexpr int s = e % ER;
+      constexpr int k = e - e / ER - 1;  // rank among the s != 0 points
       if constexpr (s != 0) {
         const uint32_t im = (q + (e / ER) * S::SLOT_STRIDE) & (NSR - 1);
-        v[e] = mul<F>(v[e], tw_r[(S::R / (NSR * ER)) * s * im]);
+        ys[k] = v[e];
+        ws[k] = tw_r[(S::R / (NSR * ER)) * s * im];
       }
+    });
+    mul_many<F, NM, mul_group<S::EL>()>(ys, ws);
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      constexpr int k = e - e / ER - 1;
+      if constexpr (e % ER != 0) v[e] = ys[k];
     });
   }
   Fe W[ER / 2 > 0 ? ER / 2 : 1];
@@ -195,27 +261,33 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
     const uint64_t idx = j + (point0(e) << log_stride);
     v[e] = load_fe(a.in, rev ? ((n - idx) & (n - 1)) : idx);
   });
+  Fe w[S::EL];  // per-point factors, multiplied in interleaved groups
   if (a.flags & kPassPreTable) {
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      v[e] = mul<F>(v[e], load_fe(a.pre_table, j + (point0(e) << log_stride)));
+      w[e] = load_fe(a.pre_table, j + (point0(e) << log_stride));
     });
+    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
   if (a.tw_pass) {  // inter-pass twiddle w_{Ns R}^(r (j mod Ns)), table [r][j mod Ns]
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      v[e] = mul<F>(v[e], load_fe(a.tw_pass, (point0(e) << a.log_ns) + (j & (ns - 1))));
+      w[e] = load_fe(a.tw_pass, (point0(e) << a.log_ns) + (j & (ns - 1)));
     });
+    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   } else if (a.tw_hi) {  // the same twiddle from the two-level tables
     const uint64_t jm = j & (ns - 1);
     const uint32_t log_mult = a.log_n - a.log_ns - LOG_R;
     const uint64_t lo_mask = (1ull << a.log_lo) - 1;
+    Fe lo[S::EL];
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
       const uint64_t ex = (point0(e) * jm) << log_mult;
-      const Fe w = mul<F>(load_fe(a.tw_hi, ex >> a.log_lo), load_fe(a.tw_lo, ex & lo_mask));
-      v[e] = mul<F>(v[e], w);
+      w[e] = load_fe(a.tw_hi, ex >> a.log_lo);
+      lo[e] = load_fe(a.tw_lo, ex & lo_mask);
     });
+    mul_many<F, S::EL, mul_group<S::EL>()>(w, lo);
+    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
 
   if constexpr (S::ROUNDS > 0) tile_round<F, LOG_R, LOG_TILE, LOG_E, 0>(v, lds, a.tw_r, c, q, writer);
@@ -229,16 +301,20 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
     return base + (r_out << a.log_ns);
   };
   if (a.flags & kPassPostTable) {
+    Fe w[S::EL];
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      v[e] = mul<F>(v[e], load_fe(a.post_table, out_index(e)));
+      w[e] = load_fe(a.post_table, out_index(e));
     });
+    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
   if (a.flags & kPassPostConst) {
+    Fe w[S::EL];
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      v[e] = mul<F>(v[e], a.post_const);
+      w[e] = a.post_const;
     });
+    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
   if (writer) {
     sfor<S::EL>([&](auto e_) {
@@ -249,7 +325,8 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
 }
 
 template <class F, int LOG_R, int LOG_TILE, int LOG_E>
-__global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS))
+__global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS),
+                                  (PassShape<LOG_R, LOG_TILE, LOG_E>::MIN_WAVES))
     ntt_pass_kernel(PassArgs a) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
   __shared__ Fe lds[S::LDS_SLOTS];

@@ -141,13 +141,69 @@ def test_forced_dependency_timeout_reports_error_and_recovers(c4, cuda):
 def test_batch_rejects_unsupported_jobs(cuda):
     from paper_2509_22684_amd import Batch, Plan, ZkError
 
-    small = Plan("bls12_381_fr", 9)
-    buf = to_dev(si.uniform_field_vector("bls12_381_fr", 1 << 9, 1), cuda)
+    # a 2-point transform has no radix-4 round
+    tiny = Plan("bls12_381_fr", 1)
+    buf = to_dev(si.uniform_field_vector("bls12_381_fr", 2, 1), cuda)
     with pytest.raises(ZkError) as e:
-        Batch([small], [buf])
+        Batch([tiny], [buf])
     assert e.value.code == -2
-    r2 = Plan("bls12_381_fr", 12, log2_radix=1)
-    buf = to_dev(si.uniform_field_vector("bls12_381_fr", 1 << 12, 1), cuda)
+    # six global passes of 2^4 points exceed the batch's four
+    deep = Plan("bls12_381_fr", 24, log2_pass_radix=4)
+    assert deep.passes == 6
+    big = torch_empty_fe(1 << 24, cuda)
     with pytest.raises(ZkError) as e:
-        Batch([r2], [buf])
+        Batch([deep], [big])
     assert e.value.code == -2
+
+
+def torch_empty_fe(n, cuda):
+    import torch
+
+    return torch.empty(n, 8, dtype=torch.int32, device=cuda)
+
+
+@pytest.mark.parametrize("log2n", [2, 3, 5, 8, 9, 11])
+def test_batch_small_jobs(cuda, log2n):
+    """Jobs below one 2^11 tile run as single-pass tiles with fewer threads
+    than the workgroup; mixed with a multi-pass job they all equal the
+    oracle."""
+    import torch
+
+    from paper_2509_22684_amd import Batch, Plan
+
+    cases = [("bls12_381_fr", log2n), ("bn254_fr", log2n), ("bls12_381_fr", 13)]
+    ins = [si.uniform_field_vector(f, 1 << L, si.stream_seed(41, L, k)) for k, (f, L) in enumerate(cases)]
+    want = [coracle.transform(f, "forward", x) for (f, _), x in zip(cases, ins)]
+    plans = [Plan(f, L) for f, L in cases]
+    bufs = _fresh_bufs(ins, cuda)
+    batch = Batch(plans, bufs)
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, f"small jobs 2^{log2n}")
+    batch.close()
+
+
+@pytest.mark.parametrize("opts", [dict(log2_radix=1), dict(log2_radix=3), dict(log2_pass_radix=6, twiddle_mode=2),
+                                  dict(log2_pass_radix=7, twiddle_mode=1)])
+def test_batch_other_schedules(cuda, opts):
+    """Plans built with other schedules batch too: the batch kernel runs each
+    plan's own pass split and twiddle source, so every job still equals the
+    oracle."""
+    import torch
+
+    from paper_2509_22684_amd import Batch, Plan
+
+    cases = [("bls12_381_fr", 10), ("bn254_fr", 12), ("bls12_381_fr", 16), ("bls12_381_fr", 18), ("bn254_fr", 18)]
+    ins = [si.uniform_field_vector(f, 1 << L, si.stream_seed(31, L, k)) for k, (f, L) in enumerate(cases)]
+    want = [coracle.transform(f, "forward", x) for (f, _), x in zip(cases, ins)]
+    job_plans = [Plan(f, L, **opts) for f, L in cases]
+    bufs = _fresh_bufs(ins, cuda)
+    batch = Batch(job_plans, bufs)
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, f"batch {opts}")
+    batch.close()
+    for p in job_plans:
+        p.close()

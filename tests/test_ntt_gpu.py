@@ -67,15 +67,16 @@ def test_size_2_20_all_kinds_and_round_trips(cuda, field):
     assert torch.equal(plan.coset_forward(outs["coset_inverse"]), dx)
 
 
-@pytest.mark.parametrize("log2n", [3, 10, 12, 16])
-def test_radix2_schedule_is_byte_identical(cuda, log2n):
-    """The radix-2 schedule (log2_radix = 1) gives the same bytes as the
-    default radix-8 schedule and the oracle."""
+@pytest.mark.parametrize("radix", [1, 2])
+@pytest.mark.parametrize("log2n", [1, 2, 3, 10, 12, 16, 19])
+def test_register_radix_schedules_are_byte_identical(cuda, log2n, radix):
+    """The radix-2 and radix-4 register schedules (log2_radix = 1, 2) give the
+    same bytes as the default radix-8 schedule and the oracle."""
     field = "bls12_381_fr"
     x = si.uniform_field_vector(field, 1 << log2n, si.stream_seed(1, 0, 0))
     dx = to_dev(x, cuda)
     p8 = _plan(field, log2n)
-    p2 = _plan(field, log2n, log2_radix=1)
+    p2 = _plan(field, log2n, log2_radix=radix)
     want = coracle.transform(field, "forward", x)
     for kind in KINDS:
         a = to_host(_run(p8, kind, dx))
