@@ -49,7 +49,7 @@ def kernel_hash() -> str:
 def traffic_from_profile(khash: str):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "ntt_pass_r256_2e24_traffic.json")
+    path = os.path.join(ROOT, "profiles", "ntt_pass_r256_t10_2e24_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -130,39 +130,60 @@ def batch_leg(dev, reps: int = 20) -> dict:
     }
 
 
-def serve_leg(dev, njobs: int = 128, rate_per_s: float = 300.0) -> dict:
-    """Quotient jobs on BLS12-381 Fr arriving as a Poisson process (seed 5,
-    log2 n uniform in [14, 22]) served with continuous batching under a
-    200 GB HBM budget.  Each job's A, B, C come from a device-resident pool
-    of one seeded vector triple per size, copied into the job's own buffers
-    on admission; latency runs from arrival to H ready on the device."""
+def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0)) -> dict:
+    """Quotient jobs on BLS12-381 Fr (log2 n uniform in [14, 22], seed 5)
+    served with continuous batching.  mu = solo throughput on the same size
+    mix (one quotient_poly call at a time); then Poisson arrivals at
+    lambda = rho mu for each rho under a 200 GB HBM budget, and once more at
+    rho = 1 under a 2 GB budget so that admission has to hold jobs back.
+    Each job's A, B, C come from a device-resident pool of one seeded vector
+    triple per size, copied into the job's own buffers on admission; latency
+    runs from arrival to H ready on the device."""
     import numpy as np
     import torch
 
     import seeded_inputs as si
     from paper_2509_22684_amd.serve import GpuExecutor, QuotientServer, Request, summarize
 
-    specs = si.serve_jobs(master=5, njobs=njobs, rate_per_s=rate_per_s)
+    sizes = [s.log2n for s in si.serve_jobs(master=5, njobs=njobs, rate_per_s=1.0)]
     pool = {}
-    for L in sorted({s.log2n for s in specs}):
+    for L in sorted(set(sizes)):
         pool[L] = tuple(torch.from_numpy(si.uniform_field_vector(FIELD, 1 << L, si.stream_seed(5, 1000 + L, v))
                                          .view(np.int32)).to(dev) for v in range(3))
-    reqs = [Request(s.job_id, s.log2n, s.arrival_s, pool[s.log2n]) for s in specs]
     ex = GpuExecutor(FIELD, dev, keep_results=False)
     for L in pool:  # plans (twiddle tables) stay resident across jobs
         ex.plan(L)
-    # warm up the kernels once
-    QuotientServer(ex, 200 << 30).run(reqs[:4], realtime=False)
-    ex.ticks = ex.tick_jobs = 0
-    srv = QuotientServer(ex, budget_bytes=200 << 30)
-    res = srv.run(reqs, realtime=True)
-    out = summarize(res)
-    out.update({"workload": f"{njobs} quotient jobs, Poisson arrivals at {rate_per_s}/s (seed 5), "
-                            "log2 n uniform in [14,22], BLS12-381 Fr, 200 GB budget",
-                "rate_per_s": rate_per_s, "ticks": ex.ticks,
-                "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "max_inflight": srv.max_inflight,
-                "peak_bytes": srv.peak_bytes})
-    return out
+
+    # mu: the size mix run solo, one job after another
+    H = {L: torch.empty_like(pool[L][0]) for L in pool}
+    for L in pool:
+        ex.plan(L).quotient(*pool[L], H[L])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for L in sizes:
+        ex.plan(L).quotient(*pool[L], H[L])
+        torch.cuda.synchronize()
+    mu = len(sizes) / (time.perf_counter() - t0)
+    del H
+
+    def run(rate: float, budget: int) -> dict:
+        specs = si.serve_jobs(master=5, njobs=njobs, rate_per_s=rate)
+        reqs = [Request(s.job_id, s.log2n, s.arrival_s, pool[s.log2n]) for s in specs]
+        ex.ticks = ex.tick_jobs = 0
+        srv = QuotientServer(ex, budget_bytes=budget)
+        res = srv.run(reqs, realtime=True)
+        out = summarize(res)
+        out.update({"rate_per_s": rate, "budget_bytes": budget, "ticks": ex.ticks,
+                    "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "max_inflight": srv.max_inflight,
+                    "peak_bytes": srv.peak_bytes})
+        return out
+
+    run(mu, 200 << 30)  # warm-up
+    runs = [dict(rho=r, **run(r * mu, 200 << 30)) for r in rhos]
+    admission = dict(rho=1.0, **run(mu, 2 << 30))
+    return {"workload": f"{njobs} quotient jobs, log2 n uniform in [14,22] (seed 5), BLS12-381 Fr, Poisson arrivals "
+                        "at rho x solo throughput",
+            "mu_solo_jobs_per_s": mu, "runs": runs, "admission_2GB": admission}
 
 
 def main() -> int:
@@ -203,13 +224,22 @@ def main() -> int:
         print(f"[bench] {args.steps} copies of {n * 32} bytes done", file=sys.stderr, flush=True)
         return 0
     if args.only == "forward":
+        # --warmup untimed forwards (clocks settle), then --steps forwards
+        # whose passes are timed with HIP events on the launch stream, the
+        # same measurement as the roofline below; prints the per-pass means.
         x = to_dev(si.uniform_field_vector(FIELD, n, si.stream_seed(3, 0, 0)))
         plan = Plan(FIELD, LOG2N)
         out = torch.empty_like(x)
-        for _ in range(args.steps):
+        work = plan.workspace(x)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(args.warmup):
             plan.forward(x, out)
         torch.cuda.synchronize()
-        print(f"[bench] {args.steps} forward NTTs at 2^{LOG2N} done", file=sys.stderr, flush=True)
+        per = [ntt_profile_passes(plan.handle, 0, x, out, work, stream) for _ in range(args.steps)]
+        pass_ms = [sum(p[k] for p in per) / len(per) for k in range(len(per[0]))]
+        print(json.dumps({"forward_passes_ms_mean": pass_ms, "avg_launch_ms": sum(pass_ms) / len(pass_ms),
+                          "warmup": args.warmup, "steps": args.steps}), flush=True)
+        print(f"[bench] {args.warmup}+{args.steps} forward NTTs at 2^{LOG2N} done", file=sys.stderr, flush=True)
         return 0
 
     print(f"[bench] generating inputs n=2^{LOG2N}", file=sys.stderr, flush=True)
@@ -263,7 +293,8 @@ def main() -> int:
     traffic = traffic_from_profile(khash)
     roofline = {
         "bound": "alu",
-        "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE=11, LOG_E={plan.opts['log2_radix'] or 2}>",
+        "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE={plan.opts['log2_tile'] or 10}, "
+                  f"LOG_E={plan.opts['log2_radix'] or 2}>",
         "achieved": achieved / 1e12,
         "peak": PEAK_MAD_PER_S / 1e12,
         "unit": "T MAD/s",

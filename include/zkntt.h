@@ -69,7 +69,9 @@ typedef struct {
   uint32_t twiddle_mode;    /* 0 default; 1 one precomputed table per pass in HBM;
                                2 two small tables and one extra multiplication per element */
   uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (2), 1 (radix-2), 2 or 3 */
-  uint32_t log2_tile;       /* elements per workgroup tile, log2: 0 default (11) or 11 */
+  uint32_t log2_tile;       /* elements per workgroup tile of a multi-pass transform, log2:
+                               0 default (10), 10 or 11 (2^11 tiles: twice the LDS, half the
+                               workgroups per CU) */
   uint32_t flags;           /* ZK_FLAG_* */
   uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (8), 4..8 */
 } ntt_plan_opts;
@@ -122,10 +124,12 @@ int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const voi
 /* ------------------------------------------------------------------------
  * Batches: many independent forward NTTs of uneven sizes and either field in
  * one persistent launch.  GPU NTTs run as short, bursty kernels with launch
- * shapes that fit some sizes badly (Section IV-A; Section V-A asks for autotuning of such parameters); a
- * batch turns every job's passes into one pass-major work list of tiles that
- * a grid of persistent workgroups drains, each tile computed exactly as in
- * the stand-alone transform (so results are byte-identical to ntt_forward).
+ * shapes that fit some sizes badly (Section IV-A; Section V-A asks for
+ * autotuning of such parameters); a batch deals its jobs' tiles into work
+ * queues (pass-major within a queue) that a grid of persistent workgroups
+ * drains.  Each queue is claimed by one XCD, so all tiles of a job run under
+ * one L2.  Every tile is computed exactly as in the stand-alone transform, so
+ * results are byte-identical to ntt_forward.
  *
  * Jobs need n >= 4 and at most 4 global passes (ZK_EUNSUPPORTED otherwise);
  * the batch computes every tile with its own radix-4 register schedule,
@@ -184,7 +188,8 @@ int ntt_batch_launch_eager(const ntt_batch *b, void *stream);
 
 /* After the stream of the last launch has been synchronised: ZK_OK, or
  * ZK_EDEVICE if a dependency wait exceeded its poll limit (the kernel then
- * stops early and the outputs are invalid). */
+ * stops early) or the launch ended with items not run; the outputs are then
+ * invalid. */
 int ntt_batch_status(const ntt_batch *b);
 
 /* Poll limit of one dependency wait (default 2^22).  0 makes every

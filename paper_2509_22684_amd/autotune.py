@@ -6,7 +6,9 @@ at run time (Section V-A).  For every (field, log2 n) this module times the
 candidate schedules of the C library on the current device — how many
 butterfly stages one global pass fuses (log2_pass_radix), where inter-pass
 twiddles come from (a precomputed table per pass, or two small tables and one
-extra multiplication), and the in-register radix — and records the fastest
+extra multiplication), the tile a workgroup holds (2^11 or 2^10 elements:
+fewer, larger workgroups or more, smaller ones per CU) and the in-register
+radix — and records the fastest
 in a JSON database keyed by device name.  Every candidate computes the same
 bytes (the GPU tests check each schedule against the oracle), so tuning only
 changes speed.
@@ -29,16 +31,16 @@ def db_path() -> str:
 
 
 def candidates(log2n: int, batchable: bool = False) -> list[dict]:
-    """Schedules to try at this size.  batchable restricts to those the
-    persistent batch kernel runs (passes of 2^5..2^8 points)."""
-    radices = (2,) if batchable else (1, 2, 3)
+    """Schedules to try at this size.  The batch kernel runs every tile with
+    its own radix-4 body on 2^11-element tiles, so batchable candidates vary
+    only the pass split and the twiddle source."""
     if log2n <= 11:
-        return [dict(log2_radix=e) for e in radices]
-    out = []
-    for e in radices:
-        for pr in (6, 7, 8):
-            for tm in (1, 2):
-                out.append(dict(log2_radix=e, log2_pass_radix=pr, twiddle_mode=tm))
+        return [dict(log2_radix=2)] if batchable else [dict(log2_radix=e) for e in (1, 2, 3)]
+    tiles = (11,) if batchable else (11, 10)
+    out = [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm, log2_tile=tile)
+           for pr in (6, 7, 8) for tm in (1, 2) for tile in tiles]
+    if not batchable:  # radix-2 and radix-8 register rounds on the default split
+        out += [dict(log2_radix=1), dict(log2_radix=3)]
     return out
 
 

@@ -73,6 +73,7 @@ struct ntt_plan {
   Fe zinv{};         // 1/(g^n - 1), Montgomery
   uint32_t twiddle_mode = 1;      // 1 table per pass, 2 two-level
   uint32_t max_log_r = 8;         // stages per global pass
+  uint32_t log_tile = 10;         // elements per workgroup tile of a multi-pass transform, log2
   Fe* tw_lo = nullptr;            // two-level mode: w_n^k, k < 2^log_lo
   Fe* tw_hi = nullptr;            //                 w_n^(k 2^log_lo)
   uint32_t log_lo = 0;
@@ -157,9 +158,9 @@ void free_plan(ntt_plan* p) {
 
 // Split log_n into passes of at most max_log_r stages each, larger radices
 // first (a single pass covers n <= 2^11 in one tile).
-std::vector<int> split_passes(uint32_t log_n, uint32_t max_log_r) {
+std::vector<int> split_passes(uint32_t log_n, uint32_t max_log_r, uint32_t log_tile) {
   std::vector<int> r;
-  if (log_n <= 11) {
+  if (log_n <= log_tile) {
     r.push_back((int)log_n);
     return r;
   }
@@ -184,13 +185,13 @@ int build_plan(ntt_plan* p) {
     p->zinv = zk::inv_mont<F>(zk::sub<F>(gn, one));
   }
 
-  std::vector<int> radices = split_passes(L, p->max_log_r);
+  std::vector<int> radices = split_passes(L, p->max_log_r, p->log_tile);
   uint32_t log_ns = 0;
   Fe* tw_r_by_log[33] = {nullptr};
   for (size_t k = 0; k < radices.size(); ++k) {
     PassDesc d{};
     d.log_r = radices[k];
-    d.log_tile = (L <= 11) ? (int)L : 11;
+    d.log_tile = (L <= p->log_tile) ? (int)L : (int)p->log_tile;
     d.log_ns = log_ns;
     if (!zk::pass_shape_supported(d.log_r, d.log_tile))
       return fail(ZK_EUNSUPPORTED, "no pass kernel for a radix-2^" + std::to_string(d.log_r) +
@@ -377,7 +378,8 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 8))
     return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..8");
   if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
-  if (!(o.log2_tile == 0 || o.log2_tile == 11)) return fail(ZK_EUNSUPPORTED, "log2_tile must be 0 or 11");
+  if (!(o.log2_tile == 0 || o.log2_tile == 10 || o.log2_tile == 11))
+    return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 10 or 11");
   if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
 
   ntt_plan* p = new (std::nothrow) ntt_plan();
@@ -389,6 +391,7 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->flags = o.flags;
   p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
   p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : 8;
+  p->log_tile = o.log2_tile ? o.log2_tile : 10;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -505,11 +508,13 @@ struct ntt_batch {
   int device = 0;
   uint32_t njobs = 0;
   uint32_t nitems = 0;
-  uint32_t nfirst = 0;  // items of BLS12-381 jobs, listed first
+  uint32_t nq_first = 0;  // queues [0, nq_first) hold BLS12-381 work, the rest BN254
+  uint32_t nq = 0;
   uint32_t grid = 0;
   void* d_mem = nullptr;
   zk::BatchJob* d_jobs = nullptr;
   zk::BatchItem* d_items = nullptr;
+  zk::BatchQueue* d_queues = nullptr;
   uint32_t* d_ctl = nullptr;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -519,6 +524,7 @@ struct ntt_batch {
 namespace {
 
 constexpr uint32_t kDefaultSpinLimit = 1u << 22;
+constexpr size_t kQueuesPerField = zk::kMaxQueues / 2;
 
 size_t batch_work_elems(const ntt_plan* const* plans, int njobs) {
   size_t total = 0;
@@ -584,8 +590,12 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     if (!sp.in || !sp.out || !aligned(sp.in) || !aligned(sp.out))
       return fail(ZK_EINVAL, "batch buffers must be non-null and 256-byte aligned");
     if (p->passes.size() > (size_t)zk::kMaxBatchPasses) return fail(ZK_EUNSUPPORTED, "too many passes for a batch");
+    // The batch picks its own tile: the whole vector up to 2^11 elements,
+    // else 2^11-element tiles (its 512-thread workgroups hold 2^11 points).
+    // A pass's arguments and tables do not depend on the tile.
+    const int batch_tile = (int)std::min<uint32_t>(p->log_n, 11);
     for (const PassDesc& d : p->passes)
-      if (!zk::batch_shape_supported(d.log_r, d.log_tile))
+      if (!zk::batch_shape_supported(d.log_r, batch_tile))
         return fail(ZK_EUNSUPPORTED, "batched launches need n >= 4 (passes of at least 4 points)");
     if (workspace_elems(p)) {
       if (!sp.work || !aligned(sp.work)) return fail(ZK_EINVAL, "batch job needs an aligned workspace");
@@ -596,26 +606,49 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     for (size_t q = 0; q < p->passes.size(); ++q) {
       J.pass[q].args = make_pass_args(p, kind, q, sp.in, sp.out, sp.work);
       J.pass[q].log_r = p->passes[q].log_r;
-      J.pass[q].log_tile = p->passes[q].log_tile;
-      J.pass[q].tiles = (uint32_t)(p->n >> p->passes[q].log_tile);
+      J.pass[q].log_tile = batch_tile;
+      J.pass[q].tiles = (uint32_t)(p->n >> batch_tile);
     }
   }
-  // Work list: the BLS12-381 jobs' items, then the BN254 jobs' items (the
-  // kernel drains the two groups in two loops, one per field); each group
-  // pass-major with larger jobs first within a pass.
-  std::vector<int> order(njobs);
-  for (int k = 0; k < njobs; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return specs[a].plan->log_n > specs[b].plan->log_n; });
+  // Work queues.  Per field, jobs are dealt largest first to the least
+  // loaded of up to kQueuesPerField queues (load = tiles over all passes);
+  // queues are listed heaviest first, BLS12-381 queues before BN254 queues,
+  // and each queue lists its items pass-major, larger jobs first.
   std::vector<zk::BatchItem> items;
-  uint32_t nfirst = 0;
+  std::vector<zk::BatchQueue> queues;
+  uint32_t nq_first = 0;
   for (uint32_t field : {(uint32_t)zk::Bls12_381Fr::ID, (uint32_t)zk::Bn254Fr::ID}) {
-    for (int q = 0; q < zk::kMaxBatchPasses; ++q)
-      for (int k : order)
-        if (jobs[k].field == field && (uint32_t)q < jobs[k].npasses)
-          for (uint32_t t = 0; t < jobs[k].pass[q].tiles; ++t)
-            items.push_back(zk::BatchItem{(uint32_t)k, (uint32_t)q, t, 0});
-    if (field == (uint32_t)zk::Bls12_381Fr::ID) nfirst = (uint32_t)items.size();
+    std::vector<int> fj;
+    for (int k = 0; k < njobs; ++k)
+      if (jobs[k].field == field) fj.push_back(k);
+    auto load = [&](int k) {
+      uint64_t t = 0;
+      for (uint32_t q = 0; q < jobs[k].npasses; ++q) t += jobs[k].pass[q].tiles;
+      return t;
+    };
+    std::stable_sort(fj.begin(), fj.end(), [&](int a, int b) { return load(a) > load(b); });
+    const size_t nq = std::min<size_t>(fj.size(), kQueuesPerField);
+    std::vector<std::vector<int>> qjobs(nq);
+    std::vector<uint64_t> qload(nq, 0);
+    for (int k : fj) {
+      const size_t q = (size_t)(std::min_element(qload.begin(), qload.end()) - qload.begin());
+      qjobs[q].push_back(k);  // jobs arrive largest first, so each queue's list is too
+      qload[q] += load(k);
+    }
+    std::vector<size_t> qorder(nq);
+    for (size_t q = 0; q < nq; ++q) qorder[q] = q;
+    std::stable_sort(qorder.begin(), qorder.end(), [&](size_t a, size_t b) { return qload[a] > qload[b]; });
+    for (size_t q : qorder) {
+      zk::BatchQueue bq{(uint32_t)items.size(), 0, field, 0};
+      for (int pass = 0; pass < zk::kMaxBatchPasses; ++pass)
+        for (int k : qjobs[q])
+          if ((uint32_t)pass < jobs[k].npasses)
+            for (uint32_t t = 0; t < jobs[k].pass[pass].tiles; ++t)
+              items.push_back(zk::BatchItem{(uint32_t)k, (uint32_t)pass, t, 0});
+      bq.size = (uint32_t)items.size() - bq.base;
+      queues.push_back(bq);
+    }
+    if (field == (uint32_t)zk::Bls12_381Fr::ID) nq_first = (uint32_t)queues.size();
   }
 
   ntt_batch* b = new (std::nothrow) ntt_batch();
@@ -623,7 +656,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->device = dev;
   b->njobs = (uint32_t)njobs;
   b->nitems = (uint32_t)items.size();
-  b->nfirst = nfirst;
+  b->nq_first = nq_first;
+  b->nq = (uint32_t)queues.size();
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
@@ -633,8 +667,9 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * zk::batch_workgroups_per_cu());
   const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
   const size_t items_bytes = ((sizeof(zk::BatchItem) * items.size() + 255) / 256) * 256;
+  const size_t queues_bytes = ((sizeof(zk::BatchQueue) * queues.size() + 255) / 256) * 256;
   const size_t ctl_words = zk::kCtlDone + (size_t)njobs * zk::kMaxBatchPasses;
-  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + ctl_words * sizeof(uint32_t));
+  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + queues_bytes + ctl_words * sizeof(uint32_t));
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "hipMalloc(batch)");
@@ -642,12 +677,15 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   char* base = static_cast<char*>(b->d_mem);
   b->d_jobs = reinterpret_cast<zk::BatchJob*>(base);
   b->d_items = reinterpret_cast<zk::BatchItem*>(base + jobs_bytes);
-  b->d_ctl = reinterpret_cast<uint32_t*>(base + jobs_bytes + items_bytes);
+  b->d_queues = reinterpret_cast<zk::BatchQueue*>(base + jobs_bytes + items_bytes);
+  b->d_ctl = reinterpret_cast<uint32_t*>(base + jobs_bytes + items_bytes + queues_bytes);
   std::vector<uint32_t> ctl(ctl_words, 0);
   ctl[zk::kCtlSpinLimit] = kDefaultSpinLimit;
   if (!jobs.empty()) e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(zk::BatchJob) * jobs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !items.empty())
     e = hipMemcpy(b->d_items, items.data(), sizeof(zk::BatchItem) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !queues.empty())
+    e = hipMemcpy(b->d_queues, queues.data(), sizeof(zk::BatchQueue) * queues.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_ctl, ctl.data(), ctl_words * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_batch(b);
@@ -658,8 +696,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->nfirst, b->d_ctl, b->njobs, b->grid,
-                                        b->capture_stream);
+      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
+                                        b->njobs, b->grid, b->capture_stream);
       e = hipStreamEndCapture(b->capture_stream, &b->graph);
       if (le != hipSuccess) e = le;
     }
@@ -725,8 +763,8 @@ int ntt_batch_launch(const ntt_batch* b, void* stream) {
 
 int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->nitems, b->nfirst, b->d_ctl, b->njobs, b->grid,
-                                  static_cast<hipStream_t>(stream));
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
+                                  b->njobs, b->grid, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
 }
 
@@ -735,7 +773,9 @@ int ntt_batch_status(const ntt_batch* b) {
   uint32_t err = 0;
   hipError_t e = hipMemcpy(&err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "batch status readback");
-  if (err) return fail(ZK_EDEVICE, "a batched dependency wait exceeded its poll limit; outputs are invalid");
+  if (err & zk::kBatchErrWait)
+    return fail(ZK_EDEVICE, "a batched dependency wait exceeded its poll limit; outputs are invalid");
+  if (err) return fail(ZK_EDEVICE, "the batch ended with items not run; outputs are invalid");
   return ZK_OK;
 }
 

@@ -5,17 +5,34 @@
 // parameters that fit some sizes badly (Section IV-A: the energy comparison of
 // Table III and the radix-256 schedule whose last kernel launches 16M
 // two-thread blocks); Section V-A asks for autotuning of such parameters.  Here a
-// batch of jobs becomes one work list of (job, pass, tile) items, ordered
-// pass-major (every job's pass 0 tiles, then every pass 1 tile, ...), with
-// larger jobs first inside a pass.  A grid of persistent workgroups pops items
-// from an atomic counter.  An item of pass p waits until all tiles of its
-// job's pass p-1 are done; because items are popped in list order, every tile
-// it waits for was popped earlier by a running workgroup, so the wait always
-// ends.  The wait is also bounded: past `spin_limit` polls the workgroup sets
-// the error flag and every workgroup exits, so a fault cannot hang the device.
+// batch of jobs becomes work queues of (job, pass, tile) items, each queue
+// pass-major (its jobs' pass 0 tiles, then their pass 1 tiles, ...), larger
+// jobs first.  A grid of persistent workgroups drains the queues.
 //
-// Each tile runs the same pass_tile code as the single-transform kernels, so
-// a job's result is bit-identical to its stand-alone transform.
+// XCD locality.  MI355X has eight XCDs, each with its own L2; the L2s are not
+// coherent with each other inside a kernel, so passing data between
+// workgroups on different XCDs needs an L2 writeback at the producer and an
+// L2 invalidate at the consumer (agent-scope release/acquire), which measured
+// slower than the transforms themselves when done once per tile.  Instead a
+// queue is claimed by one XCD (the owner word holds the XCC id read from the
+// hardware register) and only that XCD's workgroups pop from it, so every
+// tile of a job runs under one L2.  Producer and consumer then synchronise as
+// workgroups sharing an L2 do: the producer waits for its stores to complete
+// (the vector L1 writes through to L2) before counting the tile done, and
+// the consumer invalidates its CU's L1 after the count is reached.
+// Workgroups claim a new queue only when their XCD's queues have nothing
+// left to pop, which balances the XCDs dynamically.
+//
+// Progress.  An item of pass p waits until all tiles of its job's pass p-1
+// are done.  Items of a queue are popped in order by running workgroups, so
+// every tile a waiting item depends on was popped earlier by a workgroup
+// that is running it: the wait always ends.  It is also bounded: past
+// `spin_limit` polls the workgroup sets the error flag and every workgroup
+// exits, so a fault cannot hang the device.  The last workgroup to exit
+// checks that every item ran.
+//
+// Each tile computes exactly what the single-transform pass kernels compute,
+// so a job's result is bit-identical to its stand-alone transform.
 #include "ntt_batch.hpp"
 #include "ntt_pass_impl.hpp"
 
@@ -32,12 +49,28 @@ constexpr int kBatchLdsSlots = (1 << 11) + (1 << 11) / 8;
 #endif
 constexpr int kDynGroup = ZK_DYN_GROUP;
 
-// Control words are read with relaxed device-scope atomics; the one acquire
-// fence after a satisfied dependency wait and the one release fence before a
-// completion count are the only cache-maintenance points of an item.  (An
-// acquire load in the poll loop would invalidate caches on every poll.)
+// Control words are read and written with relaxed device-scope atomics.
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t xcc_id() {
+  // HW_REG_XCC_ID (hardware register 20), bits [3:0]
+  return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));
+}
+
+// Release of a finished tile to workgroups under the same L2: every thread's
+// stores have completed at L2 once its memory counters drain.
+__device__ __forceinline__ void release_to_l2() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Acquire of tiles released under the same L2: drop this CU's L1 lines so
+// the loads that follow read L2.
+__device__ __forceinline__ void acquire_from_l2() {
+  asm volatile("buffer_inv sc0" ::: "memory");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // One tile of one pass with the pass shape taken at run time: J columns x R
@@ -122,13 +155,13 @@ __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_t
       Fe ws[3];
       sfor<3>([&](auto k_) {
         constexpr int k = decltype(k_)::value;
-        ws[k] = a.tw_r[((k + 1) * im) << log_step];
+        ws[k] = load_fe(a.tw_r, ((k + 1) * im) << log_step);
       });
       detail::mul_many<F, 3, kDynGroup>(v + 1, ws);
     }
     Fe W[2];
-    W[0] = a.tw_r[0];
-    W[1] = a.tw_r[quarter];  // w_4
+    W[0] = load_fe(a.tw_r, 0);
+    W[1] = load_fe(a.tw_r, quarter);  // w_4
     detail::dft_regs<F, 2, 0>(v, W);
     const bool last = !odd && rho == r4 - 1;
     if (!last) {
@@ -159,13 +192,13 @@ __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_t
       constexpr int g = decltype(g_)::value;
       const uint32_t im = (q + g * quarter) & (nsr - 1);
       ys[g] = v[2 * g + 1];
-      ws[g] = a.tw_r[im];  // w_{2 Nsr}^im = tw_r[im R / (2 Nsr)], and R = 2 Nsr here
+      ws[g] = load_fe(a.tw_r, im);  // w_{2 Nsr}^im = tw_r[im R / (2 Nsr)], and R = 2 Nsr here
     });
     detail::mul_many<F, 2, kDynGroup>(ys, ws);
     v[1] = ys[0];
     v[3] = ys[1];
     Fe W[1];
-    W[0] = a.tw_r[0];
+    W[0] = load_fe(a.tw_r, 0);
     detail::dft_regs<F, 1, 0>(v, W);
     detail::dft_regs<F, 1, 2>(v, W);
   }
@@ -215,129 +248,194 @@ __device__ __forceinline__ void run_pointwise(const PointwiseArgs& pw, uint32_t 
 
 // Shared state of the persistent loop.
 struct QueueCtl {
-  uint32_t* head;
-  uint32_t* error;
-  uint32_t* done;
+  const BatchJob* __restrict__ jobs;
+  const BatchItem* __restrict__ items;
+  const BatchQueue* __restrict__ queues;
+  uint32_t* ctl;
   uint32_t spin_limit;
+  uint32_t me;  // this XCD's owner tag: XCC id + 1
 };
 
-constexpr uint32_t kStop = 0xffffffffu;
+// Workgroup-shared scratch of the loop; values read back from it are made
+// wave-uniform with readfirstlane, so every branch of the loop is uniform and
+// all threads reach each barrier together.  (Were the exits derived from
+// plain LDS reads, the compiler could treat them as divergent and
+// restructure the loop so that thread 0 finishes its queue work after the
+// other threads have passed the next barrier.)
+struct LoopShared {
+  uint32_t item;
+  uint32_t abort;
+  uint32_t pick;
+};
 
-// Pop the next item index for the whole workgroup, or kStop once the error
-// flag is set.  The value is made wave-uniform with readfirstlane, so every
-// loop exit below is a uniform branch and all threads reach each barrier
-// together.  (Were the exits derived from plain LDS reads, the compiler could
-// treat them as divergent and restructure the loop so that thread 0 finishes
-// its queue work after the other threads have passed the next barrier.)
-__device__ __forceinline__ uint32_t pop_item(const QueueCtl& q, uint32_t* s_item, uint32_t* s_abort) {
-  if (threadIdx.x == 0) {
-    *s_item = atomicAdd(q.head, 1u);
-    *s_abort = load_relaxed(q.error);
+constexpr uint32_t kNone = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t* queue_head(uint32_t* ctl, uint32_t q) { return ctl + kCtlQueues + 2 * q; }
+__device__ __forceinline__ uint32_t* queue_owner(uint32_t* ctl, uint32_t q) { return ctl + kCtlQueues + 2 * q + 1; }
+
+// A queue in [lo, hi) for this XCD to pop from: one it owns with items left,
+// else one it claims now; kNone when every queue of the range is claimed and
+// this XCD's are exhausted.  Wave 0 scans the queues a lane each.
+__device__ __forceinline__ uint32_t find_queue(const QueueCtl& c, uint32_t lo, uint32_t hi, LoopShared* sh) {
+  if (threadIdx.x < 64) {
+    const uint32_t q = lo + threadIdx.x;
+    const bool valid = q < hi;
+    uint32_t pick = kNone;
+    for (;;) {
+      const uint32_t owner = valid ? load_relaxed(queue_owner(c.ctl, q)) : kNone;
+      const uint32_t head = valid ? load_relaxed(queue_head(c.ctl, q)) : kNone;
+      const uint32_t size = valid ? c.queues[q].size : 0;
+      const uint64_t mine = __ballot(valid && owner == c.me && head < size);
+      if (mine) {
+        pick = lo + (uint32_t)(__ffsll((unsigned long long)mine) - 1);
+        break;
+      }
+      const uint64_t free_q = __ballot(valid && owner == 0);
+      if (!free_q) break;
+      const uint32_t lane = (uint32_t)(__ffsll((unsigned long long)free_q) - 1);
+      bool won = false;
+      if (threadIdx.x == lane) {
+        uint32_t expected = 0;
+        won = __hip_atomic_compare_exchange_strong(queue_owner(c.ctl, q), &expected, c.me, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (__ballot(won)) {
+        pick = lo + lane;
+        break;
+      }
+      // another XCD claimed that queue first; scan again (each queue is
+      // claimed once, so this ends)
+    }
+    if (threadIdx.x == 0) sh->pick = pick;
   }
   __syncthreads();
-  const uint32_t it = __builtin_amdgcn_readfirstlane(*s_item);
-  const uint32_t abort = __builtin_amdgcn_readfirstlane(*s_abort);
+  const uint32_t pick = __builtin_amdgcn_readfirstlane(sh->pick);
   __syncthreads();
-  return abort != 0 ? kStop : it;
+  return pick;
 }
 
-// Run popped items while they fall below `end` (all of them jobs on field
-// F); return the first popped index at or past `end`, or kStop.  Each field
-// has its own loop so that each loop body is register-allocated for one
-// field's arithmetic alone.
+// Pop the next index of queue q for the whole workgroup; kNone once the error
+// flag is set.
+__device__ __forceinline__ uint32_t pop(const QueueCtl& c, uint32_t q, LoopShared* sh) {
+  if (threadIdx.x == 0) {
+    sh->item = atomicAdd(queue_head(c.ctl, q), 1u);
+    sh->abort = load_relaxed(c.ctl + kCtlError);
+  }
+  __syncthreads();
+  const uint32_t it = __builtin_amdgcn_readfirstlane(sh->item);
+  const uint32_t abort = __builtin_amdgcn_readfirstlane(sh->abort);
+  __syncthreads();
+  return abort != 0 ? kNone : it;
+}
+
+// Run one item; false if its dependency wait failed.
 template <class F>
-__device__ __forceinline__ uint32_t drain(uint32_t it, uint32_t end, const BatchJob* __restrict__ jobs,
-                                          const BatchItem* __restrict__ items, const QueueCtl& q, Fe* lds,
-                                          uint32_t* s_item, uint32_t* s_abort) {
-  while (it < end) {
-    const uint32_t job_id = __builtin_amdgcn_readfirstlane(items[it].job);
-    const uint32_t pass = __builtin_amdgcn_readfirstlane(items[it].pass);
-    const uint32_t tile = __builtin_amdgcn_readfirstlane(items[it].tile);
-    const BatchJob& job = jobs[job_id];
-    if (pass > 0) {
-      if (threadIdx.x == 0) {
-        const uint32_t need = job.pass[pass - 1].tiles;
-        const uint32_t* cnt = q.done + job_id * kMaxBatchPasses + (pass - 1);
-        if (q.spin_limit == 0) {
-          atomicOr(q.error, 1u);  // test hook: every dependency wait fails at once
-        } else {
-          uint32_t spins = 0;
-          while (load_relaxed(cnt) < need) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > q.spin_limit) {
-              atomicOr(q.error, 1u);
-              break;
-            }
+__device__ __forceinline__ bool run_item(const QueueCtl& c, uint32_t it, Fe* lds, LoopShared* sh) {
+  const uint32_t job_id = __builtin_amdgcn_readfirstlane(c.items[it].job);
+  const uint32_t pass = __builtin_amdgcn_readfirstlane(c.items[it].pass);
+  const uint32_t tile = __builtin_amdgcn_readfirstlane(c.items[it].tile);
+  const BatchJob& job = c.jobs[job_id];
+  uint32_t* done = c.ctl + kCtlDone + job_id * kMaxBatchPasses;
+  if (pass > 0) {
+    if (threadIdx.x == 0) {
+      const uint32_t need = job.pass[pass - 1].tiles;
+      if (c.spin_limit == 0) {
+        atomicOr(c.ctl + kCtlError, kBatchErrWait);  // test hook: every dependency wait fails at once
+      } else {
+        uint32_t spins = 0;
+        while (load_relaxed(done + pass - 1) < need) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > c.spin_limit) {
+            atomicOr(c.ctl + kCtlError, kBatchErrWait);
+            break;
           }
         }
-        *s_abort = load_relaxed(q.error);
       }
-      __syncthreads();
-      const uint32_t failed = __builtin_amdgcn_readfirstlane(*s_abort);
-      if (failed != 0) return kStop;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      sh->abort = load_relaxed(c.ctl + kCtlError);
     }
-    const uint32_t kind = __builtin_amdgcn_readfirstlane(job.kind);
-    if (kind == kJobPointwise) {
-      run_pointwise<F>(job.pw, tile);
+    __syncthreads();
+    const uint32_t failed = __builtin_amdgcn_readfirstlane(sh->abort);
+    if (failed != 0) return false;
+    acquire_from_l2();
+  }
+  const uint32_t kind = __builtin_amdgcn_readfirstlane(job.kind);
+  if (kind == kJobPointwise) {
+    run_pointwise<F>(job.pw, tile);
+  } else {
+    const BatchPass& bp = job.pass[pass];
+    const int log_r = __builtin_amdgcn_readfirstlane(bp.log_r);
+    const int log_tile = __builtin_amdgcn_readfirstlane(bp.log_tile);
+    tile_dyn<F>(bp.args, log_r, log_tile, tile, lds);
+  }
+  release_to_l2();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(done + pass, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(c.ctl + kCtlItemsDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+// Drain this XCD's share of queues [lo, hi), all on field F; false once the
+// error flag stops the batch.  Each field has its own loop so that each loop
+// body is register-allocated for one field's arithmetic alone.
+template <class F>
+__device__ __forceinline__ bool drain(const QueueCtl& c, uint32_t lo, uint32_t hi, Fe* lds, LoopShared* sh) {
+  uint32_t q = find_queue(c, lo, hi, sh);
+  while (q != kNone) {
+    const uint32_t k = pop(c, q, sh);
+    if (k == kNone) return false;
+    if (k < c.queues[q].size) {
+      if (!run_item<F>(c, c.queues[q].base + k, lds, sh)) return false;
     } else {
-      const BatchPass& bp = job.pass[pass];
-      const int log_r = __builtin_amdgcn_readfirstlane(bp.log_r);
-      const int log_tile = __builtin_amdgcn_readfirstlane(bp.log_tile);
-      tile_dyn<F>(bp.args, log_r, log_tile, tile, lds);
+      q = find_queue(c, lo, hi, sh);
     }
-
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this thread's stores are visible device-wide
-    __syncthreads();                                     // ... for every thread of the tile
-    if (threadIdx.x == 0) {
-      __hip_atomic_fetch_add(q.done + job_id * kMaxBatchPasses + pass, 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    }
-    it = pop_item(q, s_item, s_abort);
   }
-  return it;
+  return true;
 }
 
-// Items [0, nfirst) are BLS12-381 Fr work, [nfirst, nitems) BN254 Fr work.
-// Items are popped in list order, so a workgroup leaves the first loop for
-// good once the queue passes nfirst.
-__global__ void __launch_bounds__(kBatchThreads, 4) ntt_batch_kernel(const BatchJob* __restrict__ jobs,
-                                                                 const BatchItem* __restrict__ items,
-                                                                 uint32_t nitems, uint32_t nfirst, uint32_t* ctl) {
+__global__ void __launch_bounds__(kBatchThreads, 4)
+    ntt_batch_kernel(const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items,
+                     const BatchQueue* __restrict__ queues, uint32_t nq_first, uint32_t nq, uint32_t nitems,
+                     uint32_t* ctl) {
   __shared__ Fe lds[kBatchLdsSlots];
-  __shared__ uint32_t s_item;
-  __shared__ uint32_t s_abort;
-  const QueueCtl q{ctl + kCtlHead, ctl + kCtlError, ctl + kCtlDone, ctl[kCtlSpinLimit]};
-  uint32_t it = pop_item(q, &s_item, &s_abort);
-  it = drain<Bls12_381Fr>(it, nfirst, jobs, items, q, lds, &s_item, &s_abort);
-  drain<Bn254Fr>(it, nitems, jobs, items, q, lds, &s_item, &s_abort);
+  __shared__ LoopShared sh;
+  const QueueCtl c{jobs, items, queues, ctl, ctl[kCtlSpinLimit],
+                   (uint32_t)__builtin_amdgcn_readfirstlane(xcc_id()) + 1u};
+  if (drain<Bls12_381Fr>(c, 0, nq_first, lds, &sh)) drain<Bn254Fr>(c, nq_first, nq, lds, &sh);
+
+  // The last workgroup out checks that every item ran (acquire-release on
+  // the exit count orders each workgroup's item counts before its exit).
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t exited = __hip_atomic_fetch_add(ctl + kCtlExited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (exited + 1 == gridDim.x && load_relaxed(ctl + kCtlItemsDone) != nitems)
+      atomicOr(ctl + kCtlError, kBatchErrIncomplete);
+  }
 }
 
-// Zero the queue head, the error flag and the completion counters (a kernel
-// rather than a memset so the sequence can live in a graph).
-__global__ void __launch_bounds__(256) ntt_batch_reset_kernel(uint32_t* ctl, uint32_t ndone) {
+// Zero the control words (a kernel rather than a memset so the sequence can
+// live in a graph); the poll limit is kept.
+__global__ void __launch_bounds__(256) ntt_batch_reset_kernel(uint32_t* ctl, uint32_t nwords) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    ctl[kCtlHead] = 0;
-    ctl[kCtlError] = 0;
-  }
-  if (i < ndone) ctl[kCtlDone + i] = 0;
+  if (i < nwords && i != kCtlSpinLimit) ctl[i] = 0;
 }
 
 }  // namespace
 
 bool batch_shape_supported(int log_r, int log_tile) {
-  return log_r >= 2 && log_r <= log_tile && log_tile <= 11 && (log_tile == 11 || log_r == log_tile);
+  return log_r >= 2 && log_r <= log_tile && log_tile <= 11 && (log_tile >= 10 || log_r == log_tile);
 }
 
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t nfirst,
-                        uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s) {
-  const uint32_t ndone = njobs * kMaxBatchPasses;
-  hipLaunchKernelGGL(ntt_batch_reset_kernel, dim3((ndone + 255) / 256 + 1), dim3(256), 0, s, ctl, ndone);
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues, uint32_t nq_first,
+                        uint32_t nq, uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s) {
+  const uint32_t nwords = kCtlDone + njobs * kMaxBatchPasses;
+  hipLaunchKernelGGL(ntt_batch_reset_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, ctl, nwords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nitems == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, nitems, nfirst, ctl);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, queues, nq_first, nq,
+                     nitems, ctl);
   return hipGetLastError();
 }
 

@@ -50,17 +50,42 @@ struct BatchItem {
   uint32_t pad;
 };
 
-// Control words in device memory: queue head, error flag, the poll limit of
-// a dependency wait, then one completion counter per (job, pass).
-enum : uint32_t { kCtlHead = 0, kCtlError = 1, kCtlSpinLimit = 2, kCtlDone = 4 };
+// A work queue: items [base, base + size) of the item array, all from jobs
+// on one field, pass-major.  Every job's items sit in exactly one queue, and
+// a queue is drained by the workgroups of the one XCD that claims it.
+struct BatchQueue {
+  uint32_t base;
+  uint32_t size;
+  uint32_t field;
+  uint32_t pad;
+};
+
+// At most 64 queues: one wave scans them all at once, a lane per queue.
+constexpr int kMaxQueues = 64;
+
+// Control words in device memory: error flag, poll limit of a dependency
+// wait, count of exited workgroups, count of finished items, then per queue a
+// pop counter and an owner word (0 = unclaimed, else XCC id + 1), then one
+// completion counter per (job, pass).
+enum : uint32_t {
+  kCtlError = 0,
+  kCtlSpinLimit = 1,
+  kCtlExited = 2,
+  kCtlItemsDone = 3,
+  kCtlQueues = 4,
+  kCtlDone = kCtlQueues + 2 * kMaxQueues
+};
+
+// Error flag values.
+enum : uint32_t { kBatchErrWait = 1, kBatchErrIncomplete = 2 };
 
 bool batch_shape_supported(int log_r, int log_tile);
 int batch_workgroups_per_cu();
 
 // Reset the control words of njobs jobs, then launch `grid` persistent
-// workgroups over `nitems` items, of which items [0, nfirst) belong to
-// BLS12-381 Fr jobs and the rest to BN254 Fr jobs.
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, uint32_t nitems, uint32_t nfirst,
-                        uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s);
+// workgroups over the queues: queues [0, nq_first) hold BLS12-381 Fr work,
+// [nq_first, nq) BN254 Fr work; nitems items in all.
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues, uint32_t nq_first,
+                        uint32_t nq, uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s);
 
 }  // namespace zk

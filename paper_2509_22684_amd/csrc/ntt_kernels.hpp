@@ -46,6 +46,7 @@ struct PassArgs {
 // to 2^11 points.
 inline bool pass_shape_supported(int log_r, int log_tile) {
   if (log_tile == 11) return (log_r >= 3 && log_r <= 8) || log_r == 11;
+  if (log_tile == 10 && log_r >= 3 && log_r <= 8) return true;
   return log_tile == log_r && log_r >= 0 && log_r <= 10;
 }
 

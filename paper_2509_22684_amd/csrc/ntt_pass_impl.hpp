@@ -29,9 +29,17 @@ namespace detail {
 
 constexpr __host__ __device__ int imin(int a, int b) { return a < b ? a : b; }
 
+// Vectors, tables and plan data all live in device global memory; the
+// address-space cast lets pointers loaded from descriptors (the batch kernel)
+// use global rather than flat instructions, whose completion would also hold
+// up LDS waits.
+typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const U32x4 GlobalCU4;
+typedef __attribute__((address_space(1))) U32x4 GlobalU4;
+
 __device__ __forceinline__ Fe load_fe(const Fe* __restrict__ p, uint64_t i) {
-  const uint4* q = reinterpret_cast<const uint4*>(p + i);
-  uint4 lo = q[0], hi = q[1];
+  GlobalCU4* q = (GlobalCU4*)(uintptr_t)(p + i);
+  const U32x4 lo = q[0], hi = q[1];
   Fe r;
   r.v[0] = lo.x; r.v[1] = lo.y; r.v[2] = lo.z; r.v[3] = lo.w;
   r.v[4] = hi.x; r.v[5] = hi.y; r.v[6] = hi.z; r.v[7] = hi.w;
@@ -39,9 +47,9 @@ __device__ __forceinline__ Fe load_fe(const Fe* __restrict__ p, uint64_t i) {
 }
 
 __device__ __forceinline__ void store_fe(Fe* __restrict__ p, uint64_t i, const Fe& x) {
-  uint4* q = reinterpret_cast<uint4*>(p + i);
-  q[0] = make_uint4(x.v[0], x.v[1], x.v[2], x.v[3]);
-  q[1] = make_uint4(x.v[4], x.v[5], x.v[6], x.v[7]);
+  GlobalU4* q = (GlobalU4*)(uintptr_t)(p + i);
+  q[0] = U32x4{x.v[0], x.v[1], x.v[2], x.v[3]};
+  q[1] = U32x4{x.v[4], x.v[5], x.v[6], x.v[7]};
 }
 
 // LDS slot of element e of a tile: one pad slot after every 8 elements, so
@@ -162,9 +170,12 @@ struct PassShape {
   static constexpr int ROUNDS = LOG_R == 0 ? 0 : (LOG_R + LE - 1) / LE;
   static constexpr int LDS_SLOTS = ROUNDS > 1 ? (1 << LOG_TILE) + (1 << LOG_TILE) / 8 : 1;
   static constexpr int SLOT_STRIDE = R / EL;  // threads per column
-  // Waves per SIMD the register allocation aims for: two workgroups of this
-  // tile per CU (the LDS limit) need 2 * THREADS / 256 waves on each SIMD.
-  static constexpr int MIN_WAVES = THREADS >= 256 ? 2 * THREADS / 256 : 1;
+  // Workgroups of this tile that fit a CU's 160 KiB of LDS (multi-pass tiles;
+  // single-pass shapes keep two), and the waves per SIMD the register
+  // allocation aims for so that they all stay resident: WGS * THREADS / 256.
+  static constexpr int LDS_BYTES = LDS_SLOTS * 32;
+  static constexpr int WGS = LOG_R == LOG_TILE ? 2 : imin(4, 163840 / LDS_BYTES);
+  static constexpr int MIN_WAVES = WGS * THREADS >= 256 ? WGS * THREADS / 256 : 1;
   // log2 radix of in-tile round rho: full LE except possibly the last
   static constexpr int round_log(int rho) { return imin(LE, LOG_R - rho * LE); }
 };
@@ -347,11 +358,22 @@ hipError_t launch_one(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Multi-pass tiles of 2^11 elements with radix 2^3 .. 2^8 per pass, and
+// Multi-pass tiles of 2^11 or 2^10 elements with radix 2^3 .. 2^8 per pass, and
 // single-pass transforms of up to 2^11 points held in one tile.  Keep in step
 // with pass_shape_supported().
 template <class F, int LOG_E>
 hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_t s) {
+  if (log_tile == 10 && log_r < 10) {
+    switch (log_r) {
+      case 3: return launch_one<F, 3, 10, LOG_E>(a, s);
+      case 4: return launch_one<F, 4, 10, LOG_E>(a, s);
+      case 5: return launch_one<F, 5, 10, LOG_E>(a, s);
+      case 6: return launch_one<F, 6, 10, LOG_E>(a, s);
+      case 7: return launch_one<F, 7, 10, LOG_E>(a, s);
+      case 8: return launch_one<F, 8, 10, LOG_E>(a, s);
+      default: break;
+    }
+  }
   if (log_tile == 11) {
     switch (log_r) {
       case 3: return launch_one<F, 3, 11, LOG_E>(a, s);

@@ -159,8 +159,10 @@ def test_validate_flag_rejects_noncanonical(cuda):
 
 @pytest.mark.parametrize("opts", [dict(twiddle_mode=2), dict(log2_pass_radix=6), dict(log2_pass_radix=4),
                                   dict(log2_pass_radix=7, twiddle_mode=2), dict(log2_pass_radix=5),
-                                  dict(log2_pass_radix=4, twiddle_mode=2)])
-@pytest.mark.parametrize("log2n", [12, 17, 20])
+                                  dict(log2_pass_radix=4, twiddle_mode=2), dict(log2_tile=10),
+                                  dict(log2_tile=10, log2_pass_radix=7, twiddle_mode=2),
+                                  dict(log2_tile=10, log2_radix=3), dict(log2_tile=10, log2_radix=1)])
+@pytest.mark.parametrize("log2n", [11, 12, 17, 20])
 def test_schedules_are_byte_identical(cuda, opts, log2n):
     """Every schedule the autotuner may pick (pass fusion depth, twiddle
     source) gives the oracle's bytes for all four transforms."""
