@@ -186,6 +186,61 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0)) -> dict:
             "mu_solo_jobs_per_s": mu, "runs": runs, "admission_2GB": admission}
 
 
+def host_pipeline_leg(dev, log2n: int = 22, njobs: int = 8) -> dict:
+    """Quotient jobs whose A, B, C start in pinned host memory and whose H
+    returns there: one job at a time with nothing overlapped, against the
+    three-stream pipeline that overlaps uploads, compute and downloads."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_2509_22684_amd.pipeline import HostQuotientPipeline
+
+    n = 1 << log2n
+    triples = [[torch.from_numpy(si.uniform_field_vector(FIELD, n, si.stream_seed(6, t, v)).view(np.int32))
+                .pin_memory() for v in range(3)] for t in range(2)]
+    outs = [torch.empty((n, 8), dtype=torch.int32).pin_memory() for _ in range(2)]
+    pipe = HostQuotientPipeline(FIELD, dev, depth=2)
+    pipe.run_serial(*triples[0], outs[0])  # warm-up: plan and slots
+    pipe.submit(*triples[1], outs[1]).synchronize()
+
+    t0 = time.perf_counter()
+    for k in range(njobs):
+        pipe.run_serial(*triples[k % 2], outs[k % 2])
+    serial = (time.perf_counter() - t0) / njobs
+    t0 = time.perf_counter()
+    evs = [pipe.submit(*triples[k % 2], outs[k % 2]) for k in range(njobs)]
+    for e in evs:
+        e.synchronize()
+    piped = (time.perf_counter() - t0) / njobs
+
+    # the parts alone: PCIe (three uploads, one download) and device compute
+    d = [torch.empty((n, 8), dtype=torch.int32, device=dev) for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(njobs):
+        for dst, src in zip(d[:3], triples[k % 2]):
+            dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        outs[k % 2].copy_(d[3], non_blocking=True)
+        torch.cuda.synchronize()
+    pcie = (time.perf_counter() - t0) / njobs
+    plan = pipe.plan(log2n)
+    for _ in range(2):
+        plan.quotient(d[0], d[1], d[2], d[3])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(njobs):
+        plan.quotient(d[0], d[1], d[2], d[3])
+    torch.cuda.synchronize()
+    compute = (time.perf_counter() - t0) / njobs
+    gb = 4 * n * 32 / 1e9
+    return {"workload": f"{njobs} quotient jobs at n=2^{log2n}, BLS12-381 Fr, A, B, C and H in pinned host memory",
+            "serial_ms_per_job": serial * 1e3, "pipelined_ms_per_job": piped * 1e3,
+            "pipelined_over_serial": serial / piped, "pcie_only_ms_per_job": pcie * 1e3,
+            "pcie_gb_per_job": gb, "pcie_gbs": gb / pcie, "compute_only_ms_per_job": compute * 1e3}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +249,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the host-resident pipeline leg")
     ap.add_argument("--only", choices=["forward", "copy"], default=None,
                     help="for counter runs: only run --steps forward NTTs at 2^24, or --steps plain device "
                          "copies of one 512 MiB vector (the traffic calibration kernel), then exit")
@@ -333,6 +389,9 @@ def main() -> int:
     if not args.no_serve:
         print("[bench] serving (Poisson quotient jobs)", file=sys.stderr, flush=True)
         result["serving"] = serve_leg(dev)
+    if not args.no_pipeline:
+        print("[bench] host-resident quotient pipeline", file=sys.stderr, flush=True)
+        result["host_pipeline"] = host_pipeline_leg(dev)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(host[0])

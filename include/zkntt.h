@@ -121,6 +121,23 @@ size_t quotient_workspace_bytes(const ntt_plan *p);
 int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_H,
                   void *d_work, void *stream);
 
+/* The stages of quotient_poly, for callers that interleave them with other
+ * work (e.g. start on A while B and C are still being copied to the device):
+ * quotient_poly(A, B, C, H) equals, byte for byte,
+ *   quotient_coset_evals(A -> T1); quotient_coset_evals(B -> T2);
+ *   quotient_coset_evals(C -> T3); quotient_pointwise(T1, T2, T3 -> H);
+ *   ntt_coset_inverse(H -> H).
+ *
+ * quotient_coset_evals: out = cosetNTT(INTT(in)), the values on g<w> of the
+ * polynomial that takes the values `in` on <w> (the INTT's 1/n and the coset
+ * shift g^j are fused into its last pass).  in may equal out; d_work as for
+ * ntt_forward.
+ * quotient_pointwise: out_i = (A_i B_i - C_i) / (g^n - 1) for i < n, each
+ * element read before it is written, so out may equal any input. */
+int quotient_coset_evals(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
+int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_out,
+                       void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent forward NTTs of uneven sizes and either field in
  * one persistent launch.  GPU NTTs run as short, bursty kernels with launch
@@ -128,8 +145,11 @@ int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const voi
  * autotuning of such parameters); a batch deals its jobs' tiles into work
  * queues (pass-major within a queue) that a grid of persistent workgroups
  * drains.  Each queue is claimed by one XCD, so all tiles of a job run under
- * one L2.  Every tile is computed exactly as in the stand-alone transform, so
- * results are byte-identical to ntt_forward.
+ * one L2.  A job larger than an eighth of the batch (in tiles) would be the
+ * critical path on one XCD; it runs instead as its own pass launches over the
+ * whole chip, ahead of the persistent kernel, in the same stream and graph.
+ * Every tile is computed exactly as in the stand-alone transform, so results
+ * are byte-identical to ntt_forward.
  *
  * Jobs need n >= 4 and at most 4 global passes (ZK_EUNSUPPORTED otherwise);
  * the batch computes every tile with its own radix-4 register schedule,
@@ -177,6 +197,13 @@ typedef struct {
 } ntt_batch_job;
 
 #define ZK_BATCH_GRAPH 1 /* capture the launch into a HIP graph (ntt_batch_launch) */
+/* Work queues per field, 1..32 (0: 32).  Jobs are dealt largest first to the
+ * least-loaded queue and each queue runs on one XCD: more queues balance the
+ * XCDs more finely, fewer put more independent jobs in each queue so that a
+ * tile waiting on its job's previous pass is rarer. */
+#define ZK_BATCH_QUEUES_SHIFT 8
+#define ZK_BATCH_QUEUES_MASK (0x3f << ZK_BATCH_QUEUES_SHIFT)
+#define ZK_BATCH_QUEUES(q) ((int)(q) << ZK_BATCH_QUEUES_SHIFT)
 
 int ntt_batch_create_jobs(ntt_batch **out, const ntt_batch_job *jobs, int njobs, int flags);
 

@@ -32,7 +32,9 @@ from ._lib import (  # noqa: F401
     ntt_plan_passes,
     ntt_profile_passes,
     ntt_workspace_bytes,
+    quotient_coset_evals,
     quotient_poly,
+    quotient_pointwise,
     quotient_workspace_bytes,
     zk_last_error,
 )

@@ -39,6 +39,7 @@ class _BatchJob(ctypes.Structure):
 OPS = {"forward": 0, "inverse": 1, "coset_forward": 2, "coset_inverse": 3, "inverse_to_coset": 4,
        "quotient_pointwise": 5}
 ZK_BATCH_GRAPH = 1
+ZK_BATCH_QUEUES_SHIFT = 8
 
 _lib = None
 
@@ -64,6 +65,10 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ctypes.c_int
         L.quotient_poly.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.quotient_poly.restype = ctypes.c_int
+        L.quotient_coset_evals.argtypes = [vp, vp, vp, vp, vp]
+        L.quotient_coset_evals.restype = ctypes.c_int
+        L.quotient_pointwise.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.quotient_pointwise.restype = ctypes.c_int
         L.ntt_profile_passes.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float),
                                          ctypes.c_int]
         L.ntt_profile_passes.restype = ctypes.c_int
@@ -181,6 +186,16 @@ def quotient_poly(plan, d_A, d_B, d_C, d_H, d_work, stream=None) -> None:
                                _stream(stream, d_A)), "quotient_poly")
 
 
+def quotient_coset_evals(plan, d_in, d_out, d_work=None, stream=None) -> None:
+    _check(lib().quotient_coset_evals(plan, _ptr(d_in), _ptr(d_out), _ptr(d_work), _stream(stream, d_in)),
+           "quotient_coset_evals")
+
+
+def quotient_pointwise(plan, d_A, d_B, d_C, d_out, stream=None) -> None:
+    _check(lib().quotient_pointwise(plan, _ptr(d_A), _ptr(d_B), _ptr(d_C), _ptr(d_out), _stream(stream, d_A)),
+           "quotient_pointwise")
+
+
 def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -> list:
     """Per-pass durations (ms) of one transform, from HIP events on `stream`."""
     buf = (ctypes.c_float * 64)()
@@ -259,6 +274,24 @@ class Plan:
     def coset_inverse(self, x, out=None, stream=None):
         return self._run(ntt_coset_inverse, x, out, stream)
 
+    def coset_evals(self, x, out=None, stream=None, work=None):
+        """cosetNTT(INTT(x)): the first two transforms of the quotient chain."""
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        quotient_coset_evals(self.handle, x, out, work if work is not None else self.workspace(x), stream)
+        return out
+
+    def pointwise(self, A, B, C, out=None, stream=None):
+        """(A B - C) / (g^n - 1) elementwise: the quotient chain's pointwise step."""
+        import torch
+
+        if out is None:
+            out = torch.empty_like(A)
+        quotient_pointwise(self.handle, A, B, C, out, stream)
+        return out
+
     def quotient(self, A, B, C, H=None, stream=None):
         import torch
 
@@ -300,9 +333,9 @@ def ntt_batch_create(plans, d_bufs, d_work=None) -> int:
     return h.value
 
 
-def ntt_batch_create_jobs(jobs, graph: bool = False) -> int:
+def ntt_batch_create_jobs(jobs, graph: bool = False, queues: int = 0) -> int:
     """jobs: dicts with keys plan, op (name or zk_op), in, out and optionally
-    in2, in3 (pointwise) and work."""
+    in2, in3 (pointwise) and work.  queues: work queues per field (0: default)."""
     arr = (_BatchJob * max(1, len(jobs)))()
     for k, j in enumerate(jobs):
         plan = j["plan"]
@@ -315,8 +348,8 @@ def ntt_batch_create_jobs(jobs, graph: bool = False) -> int:
         arr[k].out = _ptr(j.get("out"))
         arr[k].work = _ptr(j.get("work"))
     h = ctypes.c_void_p()
-    _check(lib().ntt_batch_create_jobs(ctypes.byref(h), arr, len(jobs), ZK_BATCH_GRAPH if graph else 0),
-           "ntt_batch_create_jobs")
+    flags = (ZK_BATCH_GRAPH if graph else 0) | (int(queues) << ZK_BATCH_QUEUES_SHIFT)
+    _check(lib().ntt_batch_create_jobs(ctypes.byref(h), arr, len(jobs), flags), "ntt_batch_create_jobs")
     return h.value
 
 
@@ -350,7 +383,7 @@ class Batch:
     """In-place forward NTTs of `bufs[k]` with `plans[k]`, one persistent launch
     replayed from a HIP graph.  Keeps plans, buffers and workspace alive."""
 
-    def __init__(self, plans, bufs, work=None):
+    def __init__(self, plans, bufs, work=None, queues: int = 0):
         import torch
 
         self.plans = list(plans)
@@ -359,7 +392,17 @@ class Batch:
         if work is None and nb:
             work = torch.empty((nb + 31) // 32, 8, dtype=torch.int32, device=self.bufs[0].device)
         self.work = work
-        self.handle = ntt_batch_create(self.plans, self.bufs, work)
+        if not queues:
+            self.handle = ntt_batch_create(self.plans, self.bufs, work)
+            return
+        # the same in-place forward jobs through the general entry point, which
+        # takes the queue count; each job gets its own slice of the workspace
+        jobs, off = [], 0
+        for p, b in zip(self.plans, self.bufs):
+            wb = lib().ntt_workspace_bytes(p.handle)
+            jobs.append(dict(plan=p, op="forward", out=b, work=work[off // 32:] if wb else None, **{"in": b}))
+            off += wb
+        self.handle = ntt_batch_create_jobs(jobs, graph=True, queues=queues)
 
     @property
     def items(self) -> int:

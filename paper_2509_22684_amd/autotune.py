@@ -32,13 +32,14 @@ def db_path() -> str:
 
 def candidates(log2n: int, batchable: bool = False) -> list[dict]:
     """Schedules to try at this size.  The batch kernel runs every tile with
-    its own radix-4 body on 2^11-element tiles, so batchable candidates vary
+    its own radix-4 body on its own tile size, so batchable candidates vary
     only the pass split and the twiddle source."""
     if log2n <= 11:
         return [dict(log2_radix=2)] if batchable else [dict(log2_radix=e) for e in (1, 2, 3)]
-    tiles = (11,) if batchable else (11, 10)
+    if batchable:
+        return [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm) for pr in (6, 7, 8) for tm in (1, 2)]
     out = [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm, log2_tile=tile)
-           for pr in (6, 7, 8) for tm in (1, 2) for tile in tiles]
+           for pr in (6, 7, 8) for tm in (1, 2) for tile in (11, 10)]
     if not batchable:  # radix-2 and radix-8 register rounds on the default split
         out += [dict(log2_radix=1), dict(log2_radix=3)]
     return out

@@ -465,6 +465,24 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
   return run_transform(p, kCosetInverse, H, H, w, s);
 }
 
+int quotient_coset_evals(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  if (int rc = transform_entry(p, kInverseToCoset, d_in, d_out, d_work, stream)) return rc;
+  return run_transform(p, kForward, d_out, d_out, d_work, static_cast<hipStream_t>(stream));
+}
+
+int quotient_pointwise(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_out,
+                       void* stream) {
+  if (!p) return fail(ZK_EINVAL, "null plan");
+  if (!d_A || !d_B || !d_C || !d_out) return fail(ZK_EINVAL, "null pointer");
+  if (!aligned(d_A) || !aligned(d_B) || !aligned(d_C) || !aligned(d_out))
+    return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
+  if (int rc = check_device(p)) return rc;
+  hipError_t e = zk::launch_quotient_pointwise(p->field, static_cast<const Fe*>(d_A), static_cast<const Fe*>(d_B),
+                                               static_cast<const Fe*>(d_C), static_cast<Fe*>(d_out), p->zinv, p->n,
+                                               static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "pointwise launch");
+}
+
 int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_out, void* d_work, void* stream,
                        float* ms_per_pass, int max_passes) {
   if (!p || !ms_per_pass) return fail(ZK_EINVAL, "null argument");
@@ -504,8 +522,21 @@ const char* zk_last_error(void) { return g_last_error.c_str(); }
 // ---------------------------------------------------------------------------
 // Batches
 
+// A batch job run as its own launches (see batch_build).
+struct DirectJob {
+  const ntt_plan* plan;
+  Kind kind;
+  bool pointwise;
+  const void* in;
+  const void* in2;
+  const void* in3;
+  void* out;
+  void* work;
+};
+
 struct ntt_batch {
   int device = 0;
+  std::vector<DirectJob> direct;
   uint32_t njobs = 0;
   uint32_t nitems = 0;
   uint32_t nq_first = 0;  // queues [0, nq_first) hold BLS12-381 work, the rest BN254
@@ -524,7 +555,7 @@ struct ntt_batch {
 namespace {
 
 constexpr uint32_t kDefaultSpinLimit = 1u << 22;
-constexpr size_t kQueuesPerField = zk::kMaxQueues / 2;
+constexpr size_t kQueuesPerField = zk::kMaxLocalQueues;
 
 size_t batch_work_elems(const ntt_plan* const* plans, int njobs) {
   size_t total = 0;
@@ -542,6 +573,24 @@ void free_batch(ntt_batch* b) {
   delete b;
 }
 
+// Everything one launch of the batch does, in stream order: the direct
+// jobs' pass launches, then the counter reset and the persistent kernel.
+int batch_enqueue(const ntt_batch* b, hipStream_t s) {
+  for (const DirectJob& d : b->direct) {
+    if (d.pointwise) {
+      hipError_t e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in),
+                                                   static_cast<const Fe*>(d.in2), static_cast<const Fe*>(d.in3),
+                                                   static_cast<Fe*>(d.out), d.plan->zinv, d.plan->n, s);
+      if (e != hipSuccess) return hip_fail(e, "pointwise launch");
+    } else if (int rc = run_transform(d.plan, d.kind, d.in, d.out, d.work, s)) {
+      return rc;
+    }
+  }
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
+                                  b->njobs, b->grid, s);
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
+}
+
 bool op_to_kind(int op, Kind* k) {
   switch (op) {
     case ZK_OP_FORWARD: *k = kForward; return true;
@@ -553,7 +602,8 @@ bool op_to_kind(int op, Kind* k) {
   }
 }
 
-int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool capture) {
+int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool capture,
+                size_t queues_per_field = kQueuesPerField) {
   if (!out) return fail(ZK_EINVAL, "null output pointer");
   *out = nullptr;
   if (njobs < 0 || (njobs > 0 && !specs)) return fail(ZK_EINVAL, "bad job array");
@@ -562,6 +612,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
 
   std::vector<zk::BatchJob> jobs(njobs);
+  std::vector<Kind> kinds(njobs, kForward);
   for (int k = 0; k < njobs; ++k) {
     const ntt_batch_job& sp = specs[k];
     const ntt_plan* p = sp.plan;
@@ -587,16 +638,18 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     }
     Kind kind;
     if (!op_to_kind(sp.op, &kind)) return fail(ZK_EINVAL, "unknown batch op " + std::to_string(sp.op));
+    kinds[k] = kind;
     if (!sp.in || !sp.out || !aligned(sp.in) || !aligned(sp.out))
       return fail(ZK_EINVAL, "batch buffers must be non-null and 256-byte aligned");
     if (p->passes.size() > (size_t)zk::kMaxBatchPasses) return fail(ZK_EUNSUPPORTED, "too many passes for a batch");
-    // The batch picks its own tile: the whole vector up to 2^11 elements,
-    // else 2^11-element tiles (its 512-thread workgroups hold 2^11 points).
-    // A pass's arguments and tables do not depend on the tile.
-    const int batch_tile = (int)std::min<uint32_t>(p->log_n, 11);
+    // The batch picks its own tile: the whole vector up to 2^kBatchTileLog
+    // elements, else tiles of that size (what its workgroups hold).  A pass's
+    // arguments and tables do not depend on the tile.
+    const int batch_tile = (int)std::min<uint32_t>(p->log_n, zk::kBatchTileLog);
     for (const PassDesc& d : p->passes)
       if (!zk::batch_shape_supported(d.log_r, batch_tile))
-        return fail(ZK_EUNSUPPORTED, "batched launches need n >= 4 (passes of at least 4 points)");
+        return fail(ZK_EUNSUPPORTED, "batched launches need n >= 4 and passes of at most 2^" +
+                                         std::to_string(zk::kBatchTileLog) + " points");
     if (workspace_elems(p)) {
       if (!sp.work || !aligned(sp.work)) return fail(ZK_EINVAL, "batch job needs an aligned workspace");
       if (sp.work == sp.in || sp.work == sp.out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
@@ -610,24 +663,32 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       J.pass[q].tiles = (uint32_t)(p->n >> batch_tile);
     }
   }
-  // Work queues.  Per field, jobs are dealt largest first to the least
-  // loaded of up to kQueuesPerField queues (load = tiles over all passes);
-  // queues are listed heaviest first, BLS12-381 queues before BN254 queues,
-  // and each queue lists its items pass-major, larger jobs first.
+  // A job larger than an eighth of the batch (load = tiles over all passes)
+  // would be the critical path on one XCD: it runs as its own pass launches
+  // over the whole chip, ahead of the persistent kernel, in the same stream.
+  auto load = [&](int k) {
+    uint64_t t = 0;
+    for (uint32_t q = 0; q < jobs[k].npasses; ++q) t += jobs[k].pass[q].tiles;
+    return t;
+  };
+  uint64_t total = 0;
+  for (int k = 0; k < njobs; ++k) total += load(k);
+  std::vector<bool> direct(njobs, false);
+  for (int k = 0; k < njobs; ++k) direct[k] = load(k) * zk::kXcds > total;
+
+  // Work queues of the other jobs.  Per field, jobs are dealt largest first
+  // to the least loaded of up to queues_per_field queues; queues are listed
+  // heaviest first, BLS12-381 queues before BN254 queues, and each queue
+  // lists its items pass-major, larger jobs first.
   std::vector<zk::BatchItem> items;
   std::vector<zk::BatchQueue> queues;
   uint32_t nq_first = 0;
   for (uint32_t field : {(uint32_t)zk::Bls12_381Fr::ID, (uint32_t)zk::Bn254Fr::ID}) {
     std::vector<int> fj;
     for (int k = 0; k < njobs; ++k)
-      if (jobs[k].field == field) fj.push_back(k);
-    auto load = [&](int k) {
-      uint64_t t = 0;
-      for (uint32_t q = 0; q < jobs[k].npasses; ++q) t += jobs[k].pass[q].tiles;
-      return t;
-    };
+      if (jobs[k].field == field && !direct[k]) fj.push_back(k);
     std::stable_sort(fj.begin(), fj.end(), [&](int a, int b) { return load(a) > load(b); });
-    const size_t nq = std::min<size_t>(fj.size(), kQueuesPerField);
+    const size_t nq = std::min<size_t>(fj.size(), queues_per_field);
     std::vector<std::vector<int>> qjobs(nq);
     std::vector<uint64_t> qload(nq, 0);
     for (int k : fj) {
@@ -658,6 +719,12 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->nitems = (uint32_t)items.size();
   b->nq_first = nq_first;
   b->nq = (uint32_t)queues.size();
+  for (int k = 0; k < njobs; ++k)
+    if (direct[k]) {
+      const ntt_batch_job& sp = specs[k];
+      b->direct.push_back(DirectJob{sp.plan, kinds[k], sp.op == ZK_OP_QUOTIENT_POINTWISE, sp.in, sp.in2, sp.in3,
+                                    sp.out, sp.work});
+    }
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
@@ -692,14 +759,17 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     return hip_fail(e, "hipMemcpy(batch descriptors)");
   }
   if (capture) {
-    // One graph: the counter reset kernel and the persistent kernel.
+    // One graph: the direct jobs' passes, the counter reset kernel and the
+    // persistent kernel.
     e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
-                                        b->njobs, b->grid, b->capture_stream);
+      const int rc = batch_enqueue(b, b->capture_stream);
       e = hipStreamEndCapture(b->capture_stream, &b->graph);
-      if (le != hipSuccess) e = le;
+      if (rc != ZK_OK) {
+        free_batch(b);
+        return rc;
+      }
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -750,8 +820,10 @@ int ntt_batch_create(ntt_batch** out, const ntt_plan* const* plans, void* const*
 }
 
 int ntt_batch_create_jobs(ntt_batch** out, const ntt_batch_job* jobs, int njobs, int flags) {
-  if (flags & ~ZK_BATCH_GRAPH) return fail(ZK_EUNSUPPORTED, "unknown batch flag bits");
-  return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0);
+  if (flags & ~(ZK_BATCH_GRAPH | ZK_BATCH_QUEUES_MASK)) return fail(ZK_EUNSUPPORTED, "unknown batch flag bits");
+  const size_t q = (size_t)((flags & ZK_BATCH_QUEUES_MASK) >> ZK_BATCH_QUEUES_SHIFT);
+  if (q > kQueuesPerField) return fail(ZK_EUNSUPPORTED, "at most 32 queues per field");
+  return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0, q ? q : kQueuesPerField);
 }
 
 int ntt_batch_launch(const ntt_batch* b, void* stream) {
@@ -763,9 +835,7 @@ int ntt_batch_launch(const ntt_batch* b, void* stream) {
 
 int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
-                                  b->njobs, b->grid, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
+  return batch_enqueue(b, static_cast<hipStream_t>(stream));
 }
 
 int ntt_batch_status(const ntt_batch* b) {

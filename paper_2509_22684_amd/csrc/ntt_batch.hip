@@ -39,11 +39,12 @@
 namespace zk {
 namespace {
 
-// Tiles of 2^11 elements computed with the radix-4 register schedule: 512
-// threads of four elements each.
+// Tiles of 2^kBatchTileLog elements computed with the radix-4 register
+// schedule: four elements per thread.
 constexpr int kBatchLogE = 2;
-constexpr int kBatchThreads = (1 << 11) >> kBatchLogE;
-constexpr int kBatchLdsSlots = (1 << 11) + (1 << 11) / 8;
+constexpr int kBatchThreads = (1 << kBatchTileLog) >> kBatchLogE;
+constexpr int kBatchLdsSlots = (1 << kBatchTileLog) + (1 << kBatchTileLog) / 8;
+constexpr int kBatchWgsPerCu = 163840 / (kBatchLdsSlots * 32);  // LDS limit
 #ifndef ZK_DYN_GROUP
 #define ZK_DYN_GROUP 2
 #endif
@@ -394,7 +395,7 @@ __device__ __forceinline__ bool drain(const QueueCtl& c, uint32_t lo, uint32_t h
   return true;
 }
 
-__global__ void __launch_bounds__(kBatchThreads, 4)
+__global__ void __launch_bounds__(kBatchThreads, kBatchWgsPerCu * kBatchThreads / 256)
     ntt_batch_kernel(const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items,
                      const BatchQueue* __restrict__ queues, uint32_t nq_first, uint32_t nq, uint32_t nitems,
                      uint32_t* ctl) {
@@ -424,7 +425,7 @@ __global__ void __launch_bounds__(256) ntt_batch_reset_kernel(uint32_t* ctl, uin
 }  // namespace
 
 bool batch_shape_supported(int log_r, int log_tile) {
-  return log_r >= 2 && log_r <= log_tile && log_tile <= 11 && (log_tile >= 10 || log_r == log_tile);
+  return log_r >= 2 && log_r <= log_tile && log_tile <= kBatchTileLog;
 }
 
 hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues, uint32_t nq_first,
@@ -439,6 +440,6 @@ hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const Batc
   return hipGetLastError();
 }
 
-int batch_workgroups_per_cu() { return 2; }  // LDS: 72 KiB per workgroup of the 160 KiB per CU
+int batch_workgroups_per_cu() { return kBatchWgsPerCu; }
 
 }  // namespace zk

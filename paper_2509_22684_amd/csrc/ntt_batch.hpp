@@ -41,7 +41,16 @@ struct BatchJob {
   uint32_t pad;
 };
 
-constexpr int kPointwiseTileLog = 11;
+// Batch tiles: 2^11 elements, 512 threads of four elements, two workgroups
+// per CU (the LDS limit).  Multi-pass jobs run in tiles of this size; jobs up
+// to this size run whole in one tile.  (2^10-element tiles, the stand-alone
+// default, measured slower here: twice the items, each with its queue pop,
+// dependency check and completion count.)
+#ifndef ZK_BATCH_TILE_LOG
+#define ZK_BATCH_TILE_LOG 11
+#endif
+constexpr int kBatchTileLog = ZK_BATCH_TILE_LOG;
+constexpr int kPointwiseTileLog = kBatchTileLog;
 
 struct BatchItem {
   uint32_t job;
@@ -60,8 +69,15 @@ struct BatchQueue {
   uint32_t pad;
 };
 
-// At most 64 queues: one wave scans them all at once, a lane per queue.
-constexpr int kMaxQueues = 64;
+// A job whose tiles exceed this fraction of the batch's tiles (1 / XCDs)
+// would be the batch's critical path on one XCD; such jobs run instead as
+// their own pass launches (all XCDs), ahead of the persistent kernel.
+constexpr int kXcds = 8;
+
+// Per field at most 32 queues: one wave scans a field's queues at once, a
+// lane per queue.
+constexpr int kMaxLocalQueues = 32;
+constexpr int kMaxQueues = 2 * kMaxLocalQueues;
 
 // Control words in device memory: error flag, poll limit of a dependency
 // wait, count of exited workgroups, count of finished items, then per queue a

@@ -35,21 +35,27 @@ constexpr __host__ __device__ int imin(int a, int b) { return a < b ? a : b; }
 // up LDS waits.
 typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const U32x4 GlobalCU4;
-typedef __attribute__((address_space(1))) U32x4 GlobalU4;
+typedef __attribute__((address_space(1))) uint32_t GlobalU32;
 
+// Two 16-byte loads per element; limbs are taken out one by one and stores go
+// limb by limb (the compiler merges them into two 16-byte stores), which
+// leaves the register allocator free to place each limb on its own.
 __device__ __forceinline__ Fe load_fe(const Fe* __restrict__ p, uint64_t i) {
   GlobalCU4* q = (GlobalCU4*)(uintptr_t)(p + i);
   const U32x4 lo = q[0], hi = q[1];
   Fe r;
-  r.v[0] = lo.x; r.v[1] = lo.y; r.v[2] = lo.z; r.v[3] = lo.w;
-  r.v[4] = hi.x; r.v[5] = hi.y; r.v[6] = hi.z; r.v[7] = hi.w;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.v[k] = lo[k];
+    r.v[4 + k] = hi[k];
+  }
   return r;
 }
 
 __device__ __forceinline__ void store_fe(Fe* __restrict__ p, uint64_t i, const Fe& x) {
-  GlobalU4* q = (GlobalU4*)(uintptr_t)(p + i);
-  q[0] = U32x4{x.v[0], x.v[1], x.v[2], x.v[3]};
-  q[1] = U32x4{x.v[4], x.v[5], x.v[6], x.v[7]};
+  GlobalU32* q = (GlobalU32*)(uintptr_t)(p + i);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) q[k] = x.v[k];
 }
 
 // LDS slot of element e of a tile: one pad slot after every 8 elements, so

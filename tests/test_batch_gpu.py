@@ -207,3 +207,50 @@ def test_batch_other_schedules(cuda, opts):
     batch.close()
     for p in job_plans:
         p.close()
+
+
+@pytest.mark.parametrize("queues", [1, 3, 8])
+def test_batch_queue_counts(c4, cuda, queues):
+    """Any number of work queues per field gives the same bytes (one queue:
+    every job of a field on one XCD; more: spread over the XCDs)."""
+    import torch
+
+    from paper_2509_22684_amd import Batch
+
+    jobs, plans, inputs, want = c4
+    job_plans = [plans[(j.field, j.log2n)] for j in jobs]
+    bufs = _fresh_bufs(inputs, cuda)
+    batch = Batch(job_plans, bufs, queues=queues)
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, f"{queues} queues per field")
+    batch.close()
+
+
+@pytest.mark.parametrize("cases", [
+    [("bls12_381_fr", 20)],
+    [("bls12_381_fr", 20), ("bls12_381_fr", 12), ("bls12_381_fr", 11), ("bn254_fr", 19), ("bn254_fr", 14)],
+    [("bn254_fr", 18), ("bn254_fr", 18), ("bls12_381_fr", 10)],
+])
+def test_batch_large_jobs_run_direct(cuda, cases):
+    """Jobs larger than an eighth of the batch run as their own pass
+    launches ahead of the persistent kernel, next to XCD-local jobs; all equal
+    the oracle, on two graph replays."""
+    import torch
+
+    from paper_2509_22684_amd import Batch, Plan
+
+    ins = [si.uniform_field_vector(f, 1 << L, si.stream_seed(51, L, k)) for k, (f, L) in enumerate(cases)]
+    want = [coracle.transform(f, "forward", x) for (f, _), x in zip(cases, ins)]
+    plans = [Plan(f, L) for f, L in cases]
+    bufs = _fresh_bufs(ins, cuda)
+    batch = Batch(plans, bufs)
+    for rep in range(2):
+        if rep:
+            _reset(bufs, ins)
+        batch.launch()
+        torch.cuda.synchronize()
+        assert batch.status() == 0
+        _check_all(bufs, want, f"large jobs {cases} launch {rep}")
+    batch.close()

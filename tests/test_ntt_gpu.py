@@ -118,6 +118,30 @@ def test_quotient_small(cuda, field, log2n):
     _check(got, coracle.quotient(field, A, B, C), f"quotient {field} 2^{log2n}")
 
 
+@pytest.mark.parametrize("field,log2n", [("bls12_381_fr", 3), ("bn254_fr", 12), ("bls12_381_fr", 17)])
+def test_quotient_stages_compose(cuda, field, log2n):
+    """quotient_coset_evals x3, quotient_pointwise and the coset inverse give
+    quotient_poly's bytes; each stage also matches its oracle definition."""
+    import torch
+
+    n = 1 << log2n
+    A, B, C = (si.uniform_field_vector(field, n, si.stream_seed(13, log2n, v)) for v in range(3))
+    plan = _plan(field, log2n)
+    dA, dB, dC = (to_dev(v, cuda) for v in (A, B, C))
+    ea = plan.coset_evals(dA)
+    _check(to_host(ea), coracle.transform(field, "coset_forward", coracle.transform(field, "inverse", A)),
+           "coset_evals(A)")
+    eb = plan.coset_evals(dB)
+    ec = dC.clone()
+    plan.coset_evals(ec, out=ec)  # in place
+    h = plan.pointwise(ea, eb, ec, out=ec)
+    plan.coset_inverse(h, out=h)
+    whole = plan.quotient(dA, dB, dC)
+    torch.cuda.synchronize()
+    assert torch.equal(h, whole)
+    _check(to_host(h), coracle.quotient(field, A, B, C), "staged quotient")
+
+
 def test_error_codes(cuda):
     import torch
 
