@@ -225,6 +225,20 @@ def host_pipeline_leg(dev, log2n: int = 22, njobs: int = 8) -> dict:
         outs[k % 2].copy_(d[3], non_blocking=True)
         torch.cuda.synchronize()
     pcie = (time.perf_counter() - t0) / njobs
+    # the same bytes with the upload (DMA) and the download (copy kernel) on
+    # two streams at once: the floor the pipeline can reach
+    from paper_2509_22684_amd import zk_copy_to_host
+
+    up, down = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(njobs):
+        with torch.cuda.stream(up):
+            for dst, src in zip(d[:3], triples[k % 2]):
+                dst.copy_(src, non_blocking=True)
+        zk_copy_to_host(outs[k % 2], d[3], n * 32, down)
+        torch.cuda.synchronize()
+    duplex = (time.perf_counter() - t0) / njobs
     plan = pipe.plan(log2n)
     for _ in range(2):
         plan.quotient(d[0], d[1], d[2], d[3])
@@ -238,7 +252,8 @@ def host_pipeline_leg(dev, log2n: int = 22, njobs: int = 8) -> dict:
     return {"workload": f"{njobs} quotient jobs at n=2^{log2n}, BLS12-381 Fr, A, B, C and H in pinned host memory",
             "serial_ms_per_job": serial * 1e3, "pipelined_ms_per_job": piped * 1e3,
             "pipelined_over_serial": serial / piped, "pcie_only_ms_per_job": pcie * 1e3,
-            "pcie_gb_per_job": gb, "pcie_gbs": gb / pcie, "compute_only_ms_per_job": compute * 1e3}
+            "pcie_gb_per_job": gb, "pcie_gbs": gb / pcie, "pcie_both_directions_ms_per_job": duplex * 1e3,
+            "compute_only_ms_per_job": compute * 1e3}
 
 
 def main() -> int:

@@ -1,6 +1,7 @@
 /*
  * zkntt: Number-Theoretic Transforms and the Groth16 quotient chain over
- * 255-bit scalar fields, on AMD Instinct MI355X (gfx950).
+ * 253- to 255-bit scalar fields (BLS12-381 Fr, BN254 Fr and BLS12-377 Fr, the
+ * curve of the paper's other workloads), on AMD Instinct MI355X (gfx950).
  *
  * What the calls compute (ZKProphet, arXiv 2509.22684):
  *   - The NTT maps a vector a = [a_0 .. a_{n-1}] of field elements to A with
@@ -13,9 +14,9 @@
  *
  * Conventions fixed by this library where the paper leaves a choice open:
  *   - n = 2^log2n, 0 <= log2n <= 2-adicity of the field (32 for BLS12-381 Fr,
- *     28 for BN254 Fr).  n = 1 is the identity transform.
+ *     28 for BN254 Fr, 47 for BLS12-377 Fr).  n = 1 is the identity transform.
  *   - w_n = g^((p-1)/n) with g the smallest multiplicative generator
- *     (g = 7 for BLS12-381 Fr, g = 5 for BN254 Fr).
+ *     (g = 7 for BLS12-381 Fr, g = 5 for BN254 Fr, g = 22 for BLS12-377 Fr).
  *   - Natural order in and out for every call.
  *   - Coset transforms evaluate on g * <w_n>: coefficient j is multiplied by
  *     g^j before the forward transform (and by g^-j after the inverse one).
@@ -54,7 +55,7 @@ extern "C" {
 
 typedef struct ntt_plan ntt_plan;
 
-typedef enum { ZK_FIELD_BLS12_381_FR = 1, ZK_FIELD_BN254_FR = 2 } zk_field;
+typedef enum { ZK_FIELD_BLS12_381_FR = 1, ZK_FIELD_BN254_FR = 2, ZK_FIELD_BLS12_377_FR = 3 } zk_field;
 
 typedef enum {
   ZK_OK = 0,
@@ -135,11 +136,21 @@ int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const voi
  * quotient_pointwise: out_i = (A_i B_i - C_i) / (g^n - 1) for i < n, each
  * element read before it is written, so out may equal any input. */
 int quotient_coset_evals(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
+
+/* Copy `bytes` (a multiple of 16; both pointers 16-byte aligned) from device
+ * memory to pinned host memory (hipHostMalloc) with a kernel, asynchronously
+ * on `stream`.  For host-resident jobs whose GPU work moves data both ways
+ * (the paper finds transfers exceed the NTT itself, Section IV-A): a DMA
+ * upload and this download keep both directions of the link busy at once,
+ * where two DMA copies in opposite directions measured as one after the
+ * other.  ZK_EINVAL if host_dst is not pinned, mapped host memory or dev_src
+ * is not device memory. */
+int zk_copy_to_host(void *host_dst, const void *dev_src, size_t bytes, void *stream);
 int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_out,
                        void *stream);
 
 /* ------------------------------------------------------------------------
- * Batches: many independent forward NTTs of uneven sizes and either field in
+ * Batches: many independent forward NTTs of uneven sizes and any field in
  * one persistent launch.  GPU NTTs run as short, bursty kernels with launch
  * shapes that fit some sizes badly (Section IV-A; Section V-A asks for
  * autotuning of such parameters); a batch deals its jobs' tiles into work

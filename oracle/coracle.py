@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ntt_oracle.c")
 LIB = os.path.join(HERE, "libntt_oracle.so")
 
-FIELD_IDS = {"bls12_381_fr": 1, "bn254_fr": 2}
+FIELD_IDS = {"bls12_381_fr": 1, "bn254_fr": 2, "bls12_377_fr": 3}
 KINDS = {"forward": 0, "inverse": 1, "coset_forward": 2, "coset_inverse": 3}
 
 

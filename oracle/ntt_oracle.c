@@ -209,17 +209,18 @@ static void field_init(field *F, const char *p_hex, uint64_t generator, int two_
   F->r_inv = finv(F, F->r_mod);
 }
 
-static field g_fields[3];
+static field g_fields[4];
 static pthread_once_t g_once = PTHREAD_ONCE_INIT;
 
 static void fields_init(void) {
   field_init(&g_fields[1], "73eda753299d7d483339d80809a1d80553bda402fffe5bfeffffffff00000001", 7, 32);
   field_init(&g_fields[2], "30644e72e131a029b85045b68181585d2833e84879b9709143e1f593f0000001", 5, 28);
+  field_init(&g_fields[3], "12ab655e9a2ca55660b44d1e5c37b00159aa76fed00000010a11800000000001", 22, 47);
 }
 
 static const field *get_field(int id) {
   pthread_once(&g_once, fields_init);
-  return (id == 1 || id == 2) ? &g_fields[id] : NULL;
+  return (id >= 1 && id <= 3) ? &g_fields[id] : NULL;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -609,8 +610,8 @@ int orc_constant(int field_id, int which, int log2n, uint32_t *out) {
       }
       return ORC_OK;
     case 2: store_limbs(out, F->r_mod); return ORC_OK;
-    case 3:
-      if (check_args(F, log2n)) return ORC_EINVAL;
+    case 3: /* any order up to the 2-adicity: no vector of that size is made */
+      if (log2n < 0 || log2n > F->two_adicity) return ORC_EINVAL;
       store_limbs(out, root_of_unity(F, log2n));
       return ORC_OK;
     default: return ORC_EINVAL;

@@ -68,7 +68,13 @@ BN254_FR = Field(
     5,
     28,
 )
-FIELDS = {f.name: f for f in (BLS12_381_FR, BN254_FR)}
+BLS12_377_FR = Field(
+    "bls12_377_fr",
+    0x12AB655E9A2CA55660B44D1E5C37B00159AA76FED00000010A11800000000001,
+    22,
+    47,
+)
+FIELDS = {f.name: f for f in (BLS12_381_FR, BN254_FR, BLS12_377_FR)}
 
 
 def _log2(n: int) -> int:

@@ -36,5 +36,6 @@ from ._lib import (  # noqa: F401
     quotient_poly,
     quotient_pointwise,
     quotient_workspace_bytes,
+    zk_copy_to_host,
     zk_last_error,
 )

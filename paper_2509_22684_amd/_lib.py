@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzkntt.so")
 
-FIELDS = {"bls12_381_fr": 1, "bn254_fr": 2}
+FIELDS = {"bls12_381_fr": 1, "bn254_fr": 2, "bls12_377_fr": 3}
 FIELD_ADICITY = {"bls12_381_fr": 32, "bn254_fr": 28}
 
 ZK_FLAG_VALIDATE = 1
@@ -69,6 +69,8 @@ def lib() -> ctypes.CDLL:
         L.quotient_coset_evals.restype = ctypes.c_int
         L.quotient_pointwise.argtypes = [vp, vp, vp, vp, vp, vp]
         L.quotient_pointwise.restype = ctypes.c_int
+        L.zk_copy_to_host.argtypes = [vp, vp, sz, vp]
+        L.zk_copy_to_host.restype = ctypes.c_int
         L.ntt_profile_passes.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float),
                                          ctypes.c_int]
         L.ntt_profile_passes.restype = ctypes.c_int
@@ -194,6 +196,14 @@ def quotient_coset_evals(plan, d_in, d_out, d_work=None, stream=None) -> None:
 def quotient_pointwise(plan, d_A, d_B, d_C, d_out, stream=None) -> None:
     _check(lib().quotient_pointwise(plan, _ptr(d_A), _ptr(d_B), _ptr(d_C), _ptr(d_out), _stream(stream, d_A)),
            "quotient_pointwise")
+
+
+def zk_copy_to_host(host_dst, dev_src, nbytes: int | None = None, stream=None) -> None:
+    """Device -> pinned host copy run by a kernel (overlaps DMA uploads)."""
+    if nbytes is None:
+        nbytes = dev_src.numel() * dev_src.element_size()
+    _check(lib().zk_copy_to_host(_ptr(host_dst), _ptr(dev_src), nbytes, _stream(stream, dev_src)),
+           "zk_copy_to_host")
 
 
 def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -> list:

@@ -144,7 +144,7 @@ def main() -> None:
     args = ap.parse_args()
     lo, hi = (int(v) for v in args.sizes.split("-"))
     db = TuningDB(args.db)
-    for field in args.field or ["bls12_381_fr", "bn254_fr"]:
+    for field in args.field or ["bls12_381_fr", "bn254_fr", "bls12_377_fr"]:
         for L in range(lo, hi + 1):
             e = tune(field, L, args.reps, args.batchable)
             db.put(field, L, e, args.batchable)

@@ -368,6 +368,7 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   int adicity = 0;
   if (field == ZK_FIELD_BLS12_381_FR) adicity = zk::Bls12_381Fr::TWO_ADICITY;
   else if (field == ZK_FIELD_BN254_FR) adicity = zk::Bn254Fr::TWO_ADICITY;
+  else if (field == ZK_FIELD_BLS12_377_FR) adicity = zk::Bls12_377Fr::TWO_ADICITY;
   else return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
   if (log2n > (uint32_t)adicity)
     return fail(ZK_EUNSUPPORTED, "log2n " + std::to_string(log2n) + " exceeds the field's 2-adicity " +
@@ -397,7 +398,9 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
     free_plan(p);
     return hip_fail(e, "hipGetDevice");
   }
-  int rc = field == ZK_FIELD_BLS12_381_FR ? build_plan<zk::Bls12_381Fr>(p) : build_plan<zk::Bn254Fr>(p);
+  int rc = field == ZK_FIELD_BLS12_381_FR ? build_plan<zk::Bls12_381Fr>(p)
+           : field == ZK_FIELD_BN254_FR    ? build_plan<zk::Bn254Fr>(p)
+                                           : build_plan<zk::Bls12_377Fr>(p);
   if (rc) {
     free_plan(p);
     return rc;
@@ -483,6 +486,31 @@ int quotient_pointwise(const ntt_plan* p, const void* d_A, const void* d_B, cons
   return e == hipSuccess ? ZK_OK : hip_fail(e, "pointwise launch");
 }
 
+int zk_copy_to_host(void* host_dst, const void* dev_src, size_t bytes, void* stream) {
+  if (!host_dst || !dev_src) return fail(ZK_EINVAL, "null pointer");
+  if (bytes % 16 || reinterpret_cast<uintptr_t>(host_dst) % 16 || reinterpret_cast<uintptr_t>(dev_src) % 16)
+    return fail(ZK_EINVAL, "bytes and both pointers must be multiples of 16");
+  hipPointerAttribute_t ha{}, da{};
+  hipError_t e = hipPointerGetAttributes(&ha, host_dst);
+  if (e != hipSuccess || ha.type != hipMemoryTypeHost) {
+    (void)hipGetLastError();
+    return fail(ZK_EINVAL, "destination must be pinned host memory (hipHostMalloc)");
+  }
+  void* mapped = nullptr;  // the destination's address as the device sees it
+  e = hipHostGetDevicePointer(&mapped, host_dst, 0);
+  if (e != hipSuccess || !mapped) {
+    (void)hipGetLastError();
+    return fail(ZK_EINVAL, "destination is not mapped for the device");
+  }
+  e = hipPointerGetAttributes(&da, dev_src);
+  if (e != hipSuccess || da.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(ZK_EINVAL, "source must be device memory");
+  }
+  e = zk::launch_copy_out(mapped, dev_src, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "copy-out launch");
+}
+
 int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_out, void* d_work, void* stream,
                        float* ms_per_pass, int max_passes) {
   if (!p || !ms_per_pass) return fail(ZK_EINVAL, "null argument");
@@ -539,8 +567,7 @@ struct ntt_batch {
   std::vector<DirectJob> direct;
   uint32_t njobs = 0;
   uint32_t nitems = 0;
-  uint32_t nq_first = 0;  // queues [0, nq_first) hold BLS12-381 work, the rest BN254
-  uint32_t nq = 0;
+  uint32_t nq_end[3] = {0, 0, 0};  // end of each field's queues: BLS12-381, BN254, BLS12-377
   uint32_t grid = 0;
   void* d_mem = nullptr;
   zk::BatchJob* d_jobs = nullptr;
@@ -586,8 +613,8 @@ int batch_enqueue(const ntt_batch* b, hipStream_t s) {
       return rc;
     }
   }
-  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_first, b->nq, b->nitems, b->d_ctl,
-                                  b->njobs, b->grid, s);
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
+                                  b->grid, s);
   return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
 }
 
@@ -678,12 +705,15 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
 
   // Work queues of the other jobs.  Per field, jobs are dealt largest first
   // to the least loaded of up to queues_per_field queues; queues are listed
-  // heaviest first, BLS12-381 queues before BN254 queues, and each queue
+  // heaviest first, BLS12-381 queues, then BN254, then BLS12-377, and each queue
   // lists its items pass-major, larger jobs first.
   std::vector<zk::BatchItem> items;
   std::vector<zk::BatchQueue> queues;
-  uint32_t nq_first = 0;
-  for (uint32_t field : {(uint32_t)zk::Bls12_381Fr::ID, (uint32_t)zk::Bn254Fr::ID}) {
+  uint32_t nq_end[3] = {0, 0, 0};
+  const uint32_t field_order[3] = {(uint32_t)zk::Bls12_381Fr::ID, (uint32_t)zk::Bn254Fr::ID,
+                                   (uint32_t)zk::Bls12_377Fr::ID};
+  for (int fi = 0; fi < 3; ++fi) {
+    const uint32_t field = field_order[fi];
     std::vector<int> fj;
     for (int k = 0; k < njobs; ++k)
       if (jobs[k].field == field && !direct[k]) fj.push_back(k);
@@ -709,7 +739,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       bq.size = (uint32_t)items.size() - bq.base;
       queues.push_back(bq);
     }
-    if (field == (uint32_t)zk::Bls12_381Fr::ID) nq_first = (uint32_t)queues.size();
+    nq_end[fi] = (uint32_t)queues.size();
   }
 
   ntt_batch* b = new (std::nothrow) ntt_batch();
@@ -717,8 +747,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->device = dev;
   b->njobs = (uint32_t)njobs;
   b->nitems = (uint32_t)items.size();
-  b->nq_first = nq_first;
-  b->nq = (uint32_t)queues.size();
+  for (int fi = 0; fi < 3; ++fi) b->nq_end[fi] = nq_end[fi];
   for (int k = 0; k < njobs; ++k)
     if (direct[k]) {
       const ntt_batch_job& sp = specs[k];

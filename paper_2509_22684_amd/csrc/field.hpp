@@ -51,6 +51,17 @@ struct Bn254Fr {
   static constexpr int ID = 2;
 };
 
+// BLS12-377 scalar field (the curve of the paper's other workloads); like
+// BLS12-381 Fr its lowest limb is 1, so INV = -1 mod 2^32.
+struct Bls12_377Fr {
+  static constexpr uint32_t P[kLimbs] = {0x00000001u, 0x0a118000u, 0xd0000001u, 0x59aa76feu,
+                                         0x5c37b001u, 0x60b44d1eu, 0x9a2ca556u, 0x12ab655eu};
+  static constexpr uint32_t INV = 0xffffffffu;
+  static constexpr int TWO_ADICITY = 47;
+  static constexpr uint32_t GENERATOR = 22;
+  static constexpr int ID = 3;
+};
+
 struct __align__(16) Fe {
   uint32_t v[kLimbs];
 };

@@ -397,13 +397,14 @@ __device__ __forceinline__ bool drain(const QueueCtl& c, uint32_t lo, uint32_t h
 
 __global__ void __launch_bounds__(kBatchThreads, kBatchWgsPerCu * kBatchThreads / 256)
     ntt_batch_kernel(const BatchJob* __restrict__ jobs, const BatchItem* __restrict__ items,
-                     const BatchQueue* __restrict__ queues, uint32_t nq_first, uint32_t nq, uint32_t nitems,
-                     uint32_t* ctl) {
+                     const BatchQueue* __restrict__ queues, uint32_t q_end0, uint32_t q_end1, uint32_t q_end2,
+                     uint32_t nitems, uint32_t* ctl) {
   __shared__ Fe lds[kBatchLdsSlots];
   __shared__ LoopShared sh;
   const QueueCtl c{jobs, items, queues, ctl, ctl[kCtlSpinLimit],
                    (uint32_t)__builtin_amdgcn_readfirstlane(xcc_id()) + 1u};
-  if (drain<Bls12_381Fr>(c, 0, nq_first, lds, &sh)) drain<Bn254Fr>(c, nq_first, nq, lds, &sh);
+  if (drain<Bls12_381Fr>(c, 0, q_end0, lds, &sh) && drain<Bn254Fr>(c, q_end0, q_end1, lds, &sh))
+    drain<Bls12_377Fr>(c, q_end1, q_end2, lds, &sh);
 
   // The last workgroup out checks that every item ran (acquire-release on
   // the exit count orders each workgroup's item counts before its exit).
@@ -428,15 +429,16 @@ bool batch_shape_supported(int log_r, int log_tile) {
   return log_r >= 2 && log_r <= log_tile && log_tile <= kBatchTileLog;
 }
 
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues, uint32_t nq_first,
-                        uint32_t nq, uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s) {
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues,
+                        const uint32_t nq_end[3], uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid,
+                        hipStream_t s) {
   const uint32_t nwords = kCtlDone + njobs * kMaxBatchPasses;
   hipLaunchKernelGGL(ntt_batch_reset_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, ctl, nwords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nitems == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, queues, nq_first, nq,
-                     nitems, ctl);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, s, jobs, items, queues, nq_end[0],
+                     nq_end[1], nq_end[2], nitems, ctl);
   return hipGetLastError();
 }
 

@@ -75,9 +75,9 @@ struct BatchQueue {
 constexpr int kXcds = 8;
 
 // Per field at most 32 queues: one wave scans a field's queues at once, a
-// lane per queue.
+// lane per queue.  Three fields.
 constexpr int kMaxLocalQueues = 32;
-constexpr int kMaxQueues = 2 * kMaxLocalQueues;
+constexpr int kMaxQueues = 3 * kMaxLocalQueues;
 
 // Control words in device memory: error flag, poll limit of a dependency
 // wait, count of exited workgroups, count of finished items, then per queue a
@@ -99,9 +99,11 @@ bool batch_shape_supported(int log_r, int log_tile);
 int batch_workgroups_per_cu();
 
 // Reset the control words of njobs jobs, then launch `grid` persistent
-// workgroups over the queues: queues [0, nq_first) hold BLS12-381 Fr work,
-// [nq_first, nq) BN254 Fr work; nitems items in all.
-hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues, uint32_t nq_first,
-                        uint32_t nq, uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid, hipStream_t s);
+// workgroups over the queues: queues [0, nq_end[0]) hold BLS12-381 Fr work,
+// [nq_end[0], nq_end[1]) BN254 Fr work, [nq_end[1], nq_end[2]) BLS12-377 Fr
+// work; nitems items in all.
+hipError_t launch_batch(const BatchJob* jobs, const BatchItem* items, const BatchQueue* queues,
+                        const uint32_t nq_end[3], uint32_t nitems, uint32_t* ctl, uint32_t njobs, uint32_t grid,
+                        hipStream_t s);
 
 }  // namespace zk

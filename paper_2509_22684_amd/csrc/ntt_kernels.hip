@@ -2,6 +2,8 @@
 // the pass dispatcher.  The pass kernels themselves are instantiated per
 // field and in-register radix in ntt_pass_<field>_e<k>.hip so they compile in
 // parallel.
+#include <algorithm>
+
 #include "ntt_kernels.hpp"
 #include "ntt_pass_impl.hpp"
 
@@ -13,6 +15,9 @@ hipError_t launch_pass_bls_e1(int log_r, int log_tile, const PassArgs& a, hipStr
 hipError_t launch_pass_bn_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_bn_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_bn_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_b377_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_b377_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_b377_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 
 namespace {
 using detail::load_fe;
@@ -72,6 +77,10 @@ hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const Pass
     if (log_e == 3) return launch_pass_bn_e3(log_r, log_tile, a, s);
     if (log_e == 2) return launch_pass_bn_e2(log_r, log_tile, a, s);
     if (log_e == 1) return launch_pass_bn_e1(log_r, log_tile, a, s);
+  } else if (field == Bls12_377Fr::ID) {
+    if (log_e == 3) return launch_pass_b377_e3(log_r, log_tile, a, s);
+    if (log_e == 2) return launch_pass_b377_e2(log_r, log_tile, a, s);
+    if (log_e == 1) return launch_pass_b377_e1(log_r, log_tile, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -81,6 +90,7 @@ hipError_t launch_gen(int field, const GenArgs& g, hipStream_t s) {
   const dim3 grid(blocks_for(g.count, 256)), block(256);
   if (field == Bls12_381Fr::ID) hipLaunchKernelGGL(gen_kernel<Bls12_381Fr>, grid, block, 0, s, g);
   else if (field == Bn254Fr::ID) hipLaunchKernelGGL(gen_kernel<Bn254Fr>, grid, block, 0, s, g);
+  else if (field == Bls12_377Fr::ID) hipLaunchKernelGGL(gen_kernel<Bls12_377Fr>, grid, block, 0, s, g);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -93,7 +103,28 @@ hipError_t launch_quotient_pointwise(int field, const Fe* a, const Fe* b, const 
     hipLaunchKernelGGL(quotient_pointwise_kernel<Bls12_381Fr>, grid, block, 0, s, a, b, c, out, zinv, n);
   else if (field == Bn254Fr::ID)
     hipLaunchKernelGGL(quotient_pointwise_kernel<Bn254Fr>, grid, block, 0, s, a, b, c, out, zinv, n);
+  else if (field == Bls12_377Fr::ID)
+    hipLaunchKernelGGL(quotient_pointwise_kernel<Bls12_377Fr>, grid, block, 0, s, a, b, c, out, zinv, n);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// Device-to-host copy on the compute units: pinned host memory is mapped into
+// the device's address space, so workgroups can store to it directly.  A DMA
+// copy in the other direction then runs at the same time (both directions of
+// the link busy at once), which two DMA copies on separate streams did not.
+__global__ void __launch_bounds__(256) copy_out_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                       uint64_t nvec) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy_out(void* host_dst, const void* dev_src, uint64_t bytes, hipStream_t s) {
+  const uint64_t nvec = bytes / 16;
+  if (nvec == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(256, (nvec + 255) / 256);
+  hipLaunchKernelGGL(copy_out_kernel, dim3(blocks), dim3(256), 0, s, static_cast<uint4*>(host_dst),
+                     static_cast<const uint4*>(dev_src), nvec);
   return hipGetLastError();
 }
 
@@ -102,6 +133,8 @@ hipError_t launch_validate(int field, const Fe* x, uint64_t n, uint32_t* d_count
   const dim3 grid(blocks_for(n, 256)), block(256);
   if (field == Bls12_381Fr::ID) hipLaunchKernelGGL(validate_kernel<Bls12_381Fr>, grid, block, 0, s, x, n, d_count);
   else if (field == Bn254Fr::ID) hipLaunchKernelGGL(validate_kernel<Bn254Fr>, grid, block, 0, s, x, n, d_count);
+  else if (field == Bls12_377Fr::ID)
+    hipLaunchKernelGGL(validate_kernel<Bls12_377Fr>, grid, block, 0, s, x, n, d_count);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -77,4 +77,8 @@ hipError_t launch_quotient_pointwise(int field, const Fe* a, const Fe* b, const 
 // Count elements with limbs >= p (non-canonical) into *d_count (device u32).
 hipError_t launch_validate(int field, const Fe* x, uint64_t n, uint32_t* d_count, hipStream_t s);
 
+// bytes (a multiple of 16) from device memory to pinned host memory, by a
+// kernel rather than a DMA engine.
+hipError_t launch_copy_out(void* host_dst, const void* dev_src, uint64_t bytes, hipStream_t s);
+
 }  // namespace zk

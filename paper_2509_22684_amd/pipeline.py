@@ -12,9 +12,14 @@ at the same time:
                     waits for B_k: quotient_coset_evals(B_k)   (overlaps C_k's copy)
                     waits for C_k: quotient_coset_evals(C_k), quotient_pointwise,
                                    ntt_coset_inverse -> H_k, event
-    d2h stream      waits for H_k: H_k -> host, event frees the slot
+    d2h stream      waits for H_k: H_k -> host (zk_copy_to_host), event frees
+                    the slot
 
-Job k + 1's uploads run while job k computes and job k - 1 downloads.  Every
+Job k + 1's uploads run while job k computes and job k - 1 downloads.  The
+uploads are DMA copies and the download is a copy kernel storing into the
+pinned host buffer: measured on MI355X, two DMA copies in opposite
+directions ran one after the other, while a DMA upload and the kernel
+download run at the same time, so both directions of the link are busy.  Every
 stage is a call of the C library on device buffers; the pipeline only orders
 them with events.  Results equal quotient_poly byte for byte.
 
@@ -83,7 +88,7 @@ class HostQuotientPipeline:
         """Queue one job: A, B, C pinned host tensors [n, 8] int32 (Montgomery
         limbs), H a pinned host tensor that receives the result.  Returns the
         event that marks H complete."""
-        from ._lib import ntt_coset_inverse, quotient_coset_evals, quotient_pointwise
+        from ._lib import ntt_coset_inverse, quotient_coset_evals, quotient_pointwise, zk_copy_to_host
 
         torch = self.torch
         n = A.shape[0]
@@ -109,10 +114,9 @@ class HostQuotientPipeline:
         ready = torch.cuda.Event()
         ready.record(cs)
         self.d2h.wait_event(ready)
-        with torch.cuda.stream(self.d2h):
-            H.copy_(s.C, non_blocking=True)
-            done = torch.cuda.Event()
-            done.record(self.d2h)
+        zk_copy_to_host(H, s.C, n * 32, self.d2h)
+        done = torch.cuda.Event()
+        done.record(self.d2h)
         s.free = done
         # the slot's device buffers are reused only after `done`; keep the
         # host tensors alive until then as well

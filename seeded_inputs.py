@@ -30,6 +30,7 @@ _M2 = np.uint64(0x94D049BB133111EB)
 MODULI = {
     "bls12_381_fr": 0x73EDA753299D7D483339D80809A1D80553BDA402FFFE5BFEFFFFFFFF00000001,
     "bn254_fr": 0x30644E72E131A029B85045B68181585D2833E84879B9709143E1F593F0000001,
+    "bls12_377_fr": 0x12AB655E9A2CA55660B44D1E5C37B00159AA76FED00000010A11800000000001,
 }
 
 

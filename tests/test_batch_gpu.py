@@ -254,3 +254,41 @@ def test_batch_large_jobs_run_direct(cuda, cases):
         assert batch.status() == 0
         _check_all(bufs, want, f"large jobs {cases} launch {rep}")
     batch.close()
+
+
+def test_batch_three_fields(cuda):
+    """BLS12-381, BN254 and BLS12-377 jobs of several sizes in one batch, each
+    field drained by its own loop of the persistent kernel, plus a pointwise
+    quotient job: all equal the oracle."""
+    import torch
+
+    from paper_2509_22684_amd import Plan, ntt_batch_create_jobs, ntt_batch_destroy, ntt_batch_launch_eager, \
+        ntt_batch_status
+
+    cases = [("bls12_377_fr", 12), ("bn254_fr", 13), ("bls12_381_fr", 11), ("bls12_377_fr", 16),
+             ("bls12_377_fr", 10), ("bn254_fr", 15), ("bls12_381_fr", 14), ("bls12_377_fr", 5)]
+    ins = [si.uniform_field_vector(f, 1 << L, si.stream_seed(61, L, k)) for k, (f, L) in enumerate(cases)]
+    plans = [Plan(f, L) for f, L in cases]
+    bufs = _fresh_bufs(ins, cuda)
+    works = [p.workspace(b) for p, b in zip(plans, bufs)]
+    # and a pointwise job on BLS12-377 Fr
+    pw_in = [si.uniform_field_vector("bls12_377_fr", 1 << 12, si.stream_seed(62, 12, v)) for v in range(3)]
+    pw_dev = _fresh_bufs(pw_in, cuda)
+    pw_out = torch.empty_like(pw_dev[0])
+    jobs = [dict(plan=p, op="forward", out=b, work=w, **{"in": b}) for p, b, w in zip(plans, bufs, works)]
+    jobs.append(dict(plan=plans[0], op="quotient_pointwise", in2=pw_dev[1], in3=pw_dev[2], out=pw_out,
+                     **{"in": pw_dev[0]}))
+    h = ntt_batch_create_jobs(jobs)
+    ntt_batch_launch_eager(h)
+    torch.cuda.synchronize()
+    assert ntt_batch_status(h) == 0
+    ntt_batch_destroy(h)
+    _check_all(bufs, [coracle.transform(f, "forward", x) for (f, _), x in zip(cases, ins)], "three fields")
+    from oracle import ref
+
+    F = ref.FIELDS["bls12_377_fr"]
+    n = 1 << 12
+    a, b_, c = (F.from_mont(si.limbs_to_ints(v)) for v in pw_in)
+    zinv = pow(pow(F.generator, n, F.p) - 1, -1, F.p)
+    want = F.to_mont([(x * y - z) * zinv % F.p for x, y, z in zip(a, b_, c)])
+    assert si.limbs_to_ints(to_host(pw_out)) == want

@@ -14,7 +14,7 @@ from tests.gpu_util import first_mismatch, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ["bls12_381_fr", "bn254_fr"]
+FIELDS = ["bls12_381_fr", "bn254_fr", "bls12_377_fr"]
 KINDS = ["forward", "inverse", "coset_forward", "coset_inverse"]
 
 
@@ -154,7 +154,10 @@ def test_error_codes(cuda):
         ntt_plan_create("bn254_fr", 29)
     assert e.value.code == -2
     with pytest.raises(ZkError) as e:
-        ntt_plan_create(3, 10)
+        ntt_plan_create("bls12_377_fr", 48)
+    assert e.value.code == -2
+    with pytest.raises(ZkError) as e:
+        ntt_plan_create(4, 10)  # no such field
     assert e.value.code == -2
     plan = _plan("bls12_381_fr", 14)
     buf = torch.zeros(2 * plan.n + 8, 8, dtype=torch.int32, device=cuda)

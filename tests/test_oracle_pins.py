@@ -27,7 +27,7 @@ import sympy
 import seeded_inputs as si
 from oracle import coracle, ref
 
-FIELDS = [ref.BLS12_381_FR, ref.BN254_FR]
+FIELDS = [ref.BLS12_381_FR, ref.BN254_FR, ref.BLS12_377_FR]
 IDS = [F.name for F in FIELDS]
 
 
@@ -296,7 +296,7 @@ def test_quotient_satisfied_r1cs_invariant(F):
 # ---------------------------------------------------------------------------
 # C oracle against the Python oracle and Horner
 
-@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr"])
+@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr", "bls12_377_fr"])
 @pytest.mark.parametrize("log2n", [0, 1, 2, 3, 4, 7, 10, 12])
 def test_c_oracle_equals_python_oracle(field, log2n):
     F = ref.FIELDS[field]
@@ -311,7 +311,7 @@ def test_c_oracle_equals_python_oracle(field, log2n):
         assert si.limbs_to_ints(coracle.quotient(field, A, B, C)) == want
 
 
-@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr"])
+@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr", "bls12_377_fr"])
 def test_c_oracle_large_n_horner(field):
     """At n = 2^16 the C oracle's outputs equal a(w^i) evaluated by Horner in
     Python integers, and its own Horner routine agrees."""
@@ -333,7 +333,7 @@ def test_c_oracle_rejects_bad_sizes():
     x = si.uniform_field_vector("bn254_fr", 4, 1)
     lib = coracle.lib()
     assert lib.orc_transform(2, 29, 0, coracle._u32(x), coracle._u32(x), 1) == -1
-    assert lib.orc_transform(3, 2, 0, coracle._u32(x), coracle._u32(x), 1) == -1
+    assert lib.orc_transform(4, 2, 0, coracle._u32(x), coracle._u32(x), 1) == -1  # unknown field id
     assert lib.orc_transform(1, 2, 9, coracle._u32(x), coracle._u32(x), 1) == -1
 
 

@@ -35,3 +35,27 @@ def test_pipeline_matches_oracle(cuda):
     H2 = torch.empty_like(H).pin_memory()
     pipe.run_serial(*host, H2)
     assert torch.equal(H, H2)
+
+
+def test_copy_to_host(cuda):
+    """The kernel download equals a DMA copy; non-pinned or misaligned
+    destinations are refused before any launch."""
+    import torch
+
+    from paper_2509_22684_amd import ZkError, zk_copy_to_host
+
+    src = torch.randint(-(1 << 31), (1 << 31) - 1, (4096 + 3, 8), dtype=torch.int32, device=cuda)
+    dst = torch.zeros((4096 + 3, 8), dtype=torch.int32).pin_memory()
+    zk_copy_to_host(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src.cpu())
+    part = torch.zeros((100, 8), dtype=torch.int32).pin_memory()
+    zk_copy_to_host(part[10:], src[:90])  # interior of a pinned buffer
+    torch.cuda.synchronize()
+    assert torch.equal(part[10:], src[:90].cpu()) and not part[:10].any()
+    with pytest.raises(ZkError) as e:
+        zk_copy_to_host(torch.zeros((16, 8), dtype=torch.int32), src[:16])  # pageable
+    assert e.value.code == -1
+    with pytest.raises(ZkError) as e:
+        zk_copy_to_host(dst, src[:16], 24)  # not a multiple of 16
+    assert e.value.code == -1
