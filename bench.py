@@ -71,6 +71,66 @@ def cpu_baseline(x_host) -> dict:
             "sample": f"one forward NTT at n=2^24 (BLS12-381 Fr) with the C oracle, {dt:.2f} s wall"}
 
 
+def cpu_one_core(log2n: int = 20) -> dict:
+    """The C oracle on one host thread, on a smaller forward NTT."""
+    import seeded_inputs as si
+    from oracle import coracle
+
+    x = si.uniform_field_vector(FIELD, 1 << log2n, si.stream_seed(2, 0, 0))
+    t0 = time.perf_counter()
+    coracle.transform(FIELD, "forward", x, threads=1)
+    dt = time.perf_counter() - t0
+    return {"value": (1 << log2n) / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"one forward NTT at n=2^{log2n} (BLS12-381 Fr) with the C oracle on one thread, {dt:.2f} s"}
+
+
+def small_configs_leg(dev) -> dict:
+    """The two smaller configurations: a radix-2 forward NTT at n = 2^12, and
+    forward, inverse, coset forward and coset inverse at n = 2^20 (with both
+    round trips checked on the device)."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_2509_22684_amd import Plan
+
+    def med(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    out = {}
+    x = torch.from_numpy(si.uniform_field_vector(FIELD, 1 << 12, si.stream_seed(1, 0, 0)).view(np.int32)).to(dev)
+    p = Plan(FIELD, 12, log2_radix=1)
+    y = torch.empty_like(x)
+    ms = med(lambda: p.forward(x, y), 50)
+    out["n2e12_radix2"] = {"us_per_forward": ms * 1e3, "elements_per_s": (1 << 12) / (ms * 1e-3),
+                           "note": "launch-bound at this size; not a roofline claim"}
+    x = torch.from_numpy(si.uniform_field_vector(FIELD, 1 << 20, si.stream_seed(2, 0, 0)).view(np.int32)).to(dev)
+    p = Plan(FIELD, 20)
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    c20 = {}
+    for kind, fn in (("forward", p.forward), ("inverse", p.inverse), ("coset_forward", p.coset_forward),
+                     ("coset_inverse", p.coset_inverse)):
+        ms = med(lambda: fn(x, y), 20)
+        c20[kind] = {"ms": ms, "elements_per_s": (1 << 20) / (ms * 1e-3)}
+    p.inverse(p.forward(x, y), z)
+    rt = torch.equal(z, x)
+    p.coset_inverse(p.coset_forward(x, y), z)
+    c20["round_trips_exact"] = rt and torch.equal(z, x)
+    out["n2e20"] = c20
+    return out
+
+
 def batch_leg(dev, reps: int = 20) -> dict:
     """64 forward NTTs (log2 n uniform in [10, 18], 48 BLS12-381 + 16 BN254):
     jobs/s for one launch sequence per NTT versus one persistent launch."""
@@ -404,6 +464,7 @@ def main() -> int:
     if not args.no_serve:
         print("[bench] serving (Poisson quotient jobs)", file=sys.stderr, flush=True)
         result["serving"] = serve_leg(dev)
+    result["small_configs"] = small_configs_leg(dev)
     if not args.no_pipeline:
         print("[bench] host-resident quotient pipeline", file=sys.stderr, flush=True)
         result["host_pipeline"] = host_pipeline_leg(dev)
@@ -412,6 +473,7 @@ def main() -> int:
         cb = cpu_baseline(host[0])
         result["cpu_baseline"] = cb
         result["gpu_over_cpu_forward"] = result["forward_ntt_2e24"]["elements_per_s"] / cb["value"]
+        result["cpu_one_core"] = cpu_one_core()
     print(json.dumps(result), flush=True)
     return 0
 

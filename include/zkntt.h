@@ -208,7 +208,7 @@ typedef struct {
 } ntt_batch_job;
 
 #define ZK_BATCH_GRAPH 1 /* capture the launch into a HIP graph (ntt_batch_launch) */
-/* Work queues per field, 1..32 (0: 32).  Jobs are dealt largest first to the
+/* Work queues per field, 1..32 (0: 16).  Jobs are dealt largest first to the
  * least-loaded queue and each queue runs on one XCD: more queues balance the
  * XCDs more finely, fewer put more independent jobs in each queue so that a
  * tile waiting on its job's previous pass is rarer. */

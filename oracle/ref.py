@@ -10,9 +10,9 @@ log2(n) stages (Fig. 4(b)).  The Groth16 prover computes the quotient h with
 forward and inverse NTTs and elementwise products (Section II, Fig. 3;
 seven NTTs, Section IV-A).
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
 * w_n = g^((p-1)/n) with g the smallest multiplicative generator
-  (7 for BLS12-381 Fr, 5 for BN254 Fr).
+  (7 for BLS12-381 Fr, 5 for BN254 Fr, 22 for BLS12-377 Fr).
 * natural order in and out; inverse = transform with w^-1, scaled by n^-1.
 * coset NTT evaluates on g*<w>: coefficient j is multiplied by g^j first.
 * quotient: H = cosetINTT((cosetNTT(INTT A) . cosetNTT(INTT B)
