@@ -173,6 +173,15 @@ def batch_leg(dev, reps: int = 20) -> dict:
         return e0.elapsed_time(e1) / reps
 
     t_per = timed(per_launch)
+    # the same per-job launch sequence captured once in a graph: what is left
+    # of the per-launch cost without host launch overhead
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for p, b, w in zip(job_plans, bufs, works):
+            p.forward(b, out=b)
+    t_per_graph = timed(g.replay)
     t_graph = timed(batch.launch)
     t_eager = timed(batch.launch_eager)
     status = batch.status()
@@ -182,6 +191,7 @@ def batch_leg(dev, reps: int = 20) -> dict:
         "workload": "64 forward NTTs, log2 n uniform in [10,18], 48 BLS12-381 Fr + 16 BN254 Fr, seed 4",
         "elements": elems,
         "per_launch": {"ms": t_per, "jobs_per_s": len(jobs) / (t_per * 1e-3), "kernel_launches": launches},
+        "per_launch_in_graph": {"ms": t_per_graph, "jobs_per_s": len(jobs) / (t_per_graph * 1e-3)},
         "batched_graph": {"ms": t_graph, "jobs_per_s": len(jobs) / (t_graph * 1e-3), "items": batch.items,
                           "workgroups": batch.grid},
         "batched_direct": {"ms": t_eager, "jobs_per_s": len(jobs) / (t_eager * 1e-3)},

@@ -39,3 +39,17 @@ def test_null_plan_calls_fail_cleanly():
     assert L.quotient_poly(None, None, None, None, None, None, None) == -1
     assert L.ntt_workspace_bytes(None) == 0
     assert b"null" in L.zk_last_error()
+    assert L.quotient_coset_evals(None, None, None, None, None) == -1
+    assert L.quotient_pointwise(None, None, None, None, None, None) == -1
+    assert L.ntt_batch_create_jobs(None, None, 0, 0) == -1
+    assert L.ntt_batch_status(None) == -1
+
+
+def test_copy_to_host_checks_before_launch():
+    """Null, misaligned or odd-sized copies are refused before any HIP call."""
+    from paper_2509_22684_amd import _lib
+
+    L = _lib.lib()
+    assert L.zk_copy_to_host(None, None, 16, None) == -1
+    assert L.zk_copy_to_host(ctypes.c_void_p(256), ctypes.c_void_p(512), 24, None) == -1
+    assert L.zk_copy_to_host(ctypes.c_void_p(8), ctypes.c_void_p(512), 32, None) == -1
