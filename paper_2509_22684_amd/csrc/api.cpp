@@ -341,6 +341,26 @@ int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void*
 
 size_t workspace_elems(const ntt_plan* p) { return p->passes.size() >= 2 ? p->n : 0; }
 
+// Forward NTT of `in` whose last pass also applies the quotient's pointwise
+// step with the coset evaluations a and b: out = (a b - NTT(in)) / (g^n - 1).
+int run_forward_pointwise(const ntt_plan* p, const void* in, void* out, void* work, const Fe* a, const Fe* b,
+                          hipStream_t s) {
+  const size_t P = p->passes.size();
+  for (size_t k = 0; k < P; ++k) {
+    const PassDesc& d = p->passes[k];
+    zk::PassArgs args = make_pass_args(p, kForward, k, in, out, work);
+    if (k + 1 == P) {
+      args.flags |= zk::kPassPostPointwise;
+      args.pw_a = a;
+      args.pw_b = b;
+      args.post_const = p->zinv;
+    }
+    hipError_t e = zk::launch_pass(p->field, d.log_r, d.log_tile, p->log_e, args, s);
+    if (e != hipSuccess) return hip_fail(e, "NTT pass launch");
+  }
+  return ZK_OK;
+}
+
 int transform_entry(const ntt_plan* p, Kind kind, const void* in, void* out, void* work, void* stream) {
   if (!p) return fail(ZK_EINVAL, "null plan");
   if (!in || !out) return fail(ZK_EINVAL, "null vector pointer");
@@ -456,15 +476,19 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
   Fe* w = workspace_elems(p) ? t2 + p->n : nullptr;
   Fe* H = static_cast<Fe*>(d_H);
   // Each of A, B, C: INTT with the coset shift g^k and 1/n fused in its last
-  // pass, then a forward NTT: evaluations on g<w>.
+  // pass, then a forward NTT: evaluations on g<w>.  The last pass of C's
+  // forward NTT also applies the pointwise step (A B - C) / (g^n - 1), so H
+  // holds the quotient's coset values without a separate pass over memory.
   const void* src[3] = {d_A, d_B, d_C};
   Fe* dst[3] = {t1, t2, H};
   for (int v = 0; v < 3; ++v) {
     if (int rc = run_transform(p, kInverseToCoset, src[v], dst[v], w, s)) return rc;
-    if (int rc = run_transform(p, kForward, dst[v], dst[v], w, s)) return rc;
+    if (v < 2) {
+      if (int rc = run_transform(p, kForward, dst[v], dst[v], w, s)) return rc;
+    } else if (int rc = run_forward_pointwise(p, H, H, w, t1, t2, s)) {
+      return rc;
+    }
   }
-  hipError_t e = zk::launch_quotient_pointwise(p->field, t1, t2, H, H, p->zinv, p->n, s);
-  if (e != hipSuccess) return hip_fail(e, "pointwise launch");
   return run_transform(p, kCosetInverse, H, H, w, s);
 }
 

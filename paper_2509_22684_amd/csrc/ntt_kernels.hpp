@@ -13,6 +13,7 @@ enum PassFlags : uint32_t {
   kPassPreTable = 2u,    // first pass: multiply input idx by pre_table[idx]
   kPassPostTable = 4u,   // last pass: multiply output k by post_table[k]
   kPassPostConst = 8u,   // last pass: multiply every output by post_const
+  kPassPostPointwise = 16u,  // last pass: out_k = (pw_a[k] pw_b[k] - out_k) post_const
 };
 
 // Arguments of one global radix-R Stockham pass over n = 2^log_n elements.
@@ -34,7 +35,9 @@ struct PassArgs {
   const Fe* tw_hi;       // w_n^(k 2^log_lo)    (two-level mode)
   const Fe* pre_table;   // see kPassPreTable
   const Fe* post_table;  // see kPassPostTable
-  Fe post_const;         // see kPassPostConst
+  const Fe* pw_a;        // see kPassPostPointwise
+  const Fe* pw_b;
+  Fe post_const;         // see kPassPostConst, kPassPostPointwise
   uint32_t log_n;
   uint32_t log_ns;
   uint32_t flags;

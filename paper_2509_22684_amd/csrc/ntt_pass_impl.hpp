@@ -333,6 +333,19 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
     });
     mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
+  if (a.flags & kPassPostPointwise) {
+    // the quotient's pointwise step fused into the last pass of the third
+    // coset NTT: (A B - C) / (g^n - 1) with C this pass's output, in the
+    // same operation order as quotient_pointwise_kernel
+    // (one element at a time: this runs once per quotient, and holding the
+    // operands of all elements at once would cost registers everywhere)
+    sfor<S::EL>([&](auto e_) {
+      constexpr int e = decltype(e_)::value;
+      const uint64_t k = out_index(e);
+      const Fe ab = mul<F>(load_fe(a.pw_a, k), load_fe(a.pw_b, k));
+      v[e] = mul<F>(sub<F>(ab, v[e]), a.post_const);
+    });
+  }
   if (writer) {
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
