@@ -292,3 +292,17 @@ def test_batch_three_fields(cuda):
     zinv = pow(pow(F.generator, n, F.p) - 1, -1, F.p)
     want = F.to_mont([(x * y - z) * zinv % F.p for x, y, z in zip(a, b_, c)])
     assert si.limbs_to_ints(to_host(pw_out)) == want
+
+
+def test_empty_batch(cuda):
+    """A batch of no jobs launches (only the counter reset runs) and reports
+    success."""
+    import torch
+
+    from paper_2509_22684_amd import ntt_batch_create_jobs, ntt_batch_destroy, ntt_batch_launch, ntt_batch_status
+
+    h = ntt_batch_create_jobs([], graph=True)
+    ntt_batch_launch(h)
+    torch.cuda.synchronize()
+    assert ntt_batch_status(h) == 0
+    ntt_batch_destroy(h)

@@ -61,3 +61,18 @@ def test_staggered_arrivals_and_tight_budget(cuda):
     assert srv.peak_bytes <= budget
     assert 1 <= srv.max_inflight < len(reqs)
     _check(res, reqs, cuda)
+
+
+@pytest.mark.slow
+def test_serving_sizes_up_to_2_22(cuda):
+    """The serving size range at its ends: a 2^22 job (a stage of it larger
+    than an eighth of the tick runs as direct pass launches) beside small
+    ones; every H equals the oracle's quotient in full."""
+    from paper_2509_22684_amd.serve import GpuExecutor, QuotientServer
+
+    reqs = _requests([22, 14, 18, 14])
+    ex = GpuExecutor(FIELD)
+    res = QuotientServer(ex, budget_bytes=200 << 30).run(reqs, realtime=False)
+    for r, q in zip(res, reqs):
+        assert r.status == "done"
+        assert np.array_equal(to_host(r.H), coracle.quotient(FIELD, *q.inputs)), f"job {q.job_id} (2^{q.log2n})"
