@@ -234,7 +234,8 @@ int ntt_batch_status(const ntt_batch *b);
  * dependency wait fail at once (a test hook for the error path).  Synchronous. */
 int ntt_batch_set_spin_limit(ntt_batch *b, uint32_t polls);
 
-/* Work items (tiles) in the batch and persistent workgroups per launch. */
+/* Work items (tiles) the persistent kernel drains (jobs run as direct pass
+ * launches are not counted) and persistent workgroups per launch. */
 int ntt_batch_items(const ntt_batch *b);
 int ntt_batch_grid(const ntt_batch *b);
 
