@@ -11,10 +11,12 @@
 // base computed on the host, so plan creation costs milliseconds even at
 // n = 2^24.
 //
-// Transforms are sequences of Stockham passes (ntt_kernels.hip); the inverse
-// runs the forward passes on the index-reversed input, since
+// Transforms are sequences of Stockham passes (ntt_pass_impl.hpp, one
+// translation unit per field and register radix); the inverse runs the
+// forward passes on the index-reversed input, since
 // sum_i X_i w^(-ij) = sum_i X_(-i mod n) w^(ij), and scales by 1/n on the
-// last pass.
+// last pass.  Batches (ntt_batch.hip) reuse the plans' tables and pass
+// arguments.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -157,7 +159,7 @@ void free_plan(ntt_plan* p) {
 }
 
 // Split log_n into passes of at most max_log_r stages each, larger radices
-// first (a single pass covers n <= 2^11 in one tile).
+// first (a single pass covers n up to the tile size in one tile).
 std::vector<int> split_passes(uint32_t log_n, uint32_t max_log_r, uint32_t log_tile) {
   std::vector<int> r;
   if (log_n <= log_tile) {

@@ -82,7 +82,8 @@ __device__ __forceinline__ void acquire_from_l2() {
 // computed at run time, so the persistent loop holds one tile body per field
 // and its register allocation is that of a single shape.  Threads t >=
 // 2^(log_tile - 2) shadow thread t mod 2^(log_tile - 2) and store nothing.
-// log_r and log_tile are wave-uniform; 2 <= log_r <= log_tile <= 11.
+// log_r and log_tile are wave-uniform; 2 <= log_r <= log_tile <= 11.  (Batch
+// jobs never carry kPassPostPointwise: the pointwise step is a job of its own.)
 template <class F>
 __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_tile, uint32_t tile, Fe* lds) {
   using detail::lds_slot;
