@@ -59,6 +59,19 @@ def traffic_from_profile(khash: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def valu_from_profile(khash: str):
+    """VALU wave instructions per launch of the dominant kernel from the
+    committed rocprofv3 counter summary, if taken on the current source."""
+    path = os.path.join(ROOT, "profiles", "ntt_pass_r256_t10_2e24_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != khash:
+        return None
+    return d.get("valu_wave_instructions_per_launch")
+
+
 def cpu_baseline(x_host) -> dict:
     """The C oracle on the host cores: one forward NTT at n = 2^24."""
     from oracle import coracle
@@ -432,6 +445,7 @@ def main() -> int:
     achieved = mads_per_launch / (avg_pass_ms * 1e-3)
     khash = kernel_hash()
     traffic = traffic_from_profile(khash)
+    valu = valu_from_profile(khash)
     roofline = {
         "bound": "alu",
         "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE={plan.opts['log2_tile'] or 10}, "
@@ -445,6 +459,10 @@ def main() -> int:
         "pass_ms": pass_ms,
         "algorithmic_mads_per_launch": mads_per_launch,
         "hbm_gbs_min_traffic": (2 * n * 32 + (n * 32 if npass > 1 else 0)) / (avg_pass_ms * 1e-3) / 1e9,
+        # the same kernel against the VALU issue peak (every wave64 VALU
+        # instruction is 64 lane operations): how busy the kernel keeps the
+        # units the MAD roofline is drawn on, counted instructions / time
+        "valu_issue_frac": (valu * 64 / (avg_pass_ms * 1e-3) / PEAK_MAD_PER_S) if valu else None,
         "kernel_source_hash": khash,
     }
 
