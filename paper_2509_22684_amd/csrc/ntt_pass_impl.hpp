@@ -184,6 +184,12 @@ struct PassShape {
   static constexpr int MIN_WAVES = WGS * THREADS >= 256 ? WGS * THREADS / 256 : 1;
   // log2 radix of in-tile round rho: full LE except possibly the last
   static constexpr int round_log(int rho) { return imin(LE, LOG_R - rho * LE); }
+  // Wave-major slot numbering (see pass_tile): with four elements per thread,
+  // whole waves per column group and a multiple of four waves, every wave
+  // holds slots q of one residue mod 4, so the twiddles of in-tile round 1,
+  // w^(s (q mod 4)), are all 1 for a whole wave out of four.
+  static constexpr int WAVES = THREADS / 64;
+  static constexpr bool WAVE_Q = EL == 4 && THREADS >= 256 && WAVES % 4 == 0 && J <= 64 && LOG_R >= 4;
 };
 
 // One in-tile round rho (radix Er = 2^LR, earlier in-tile radices' product
@@ -211,23 +217,30 @@ __device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __rest
     });
     // in-tile twiddles of the points with s = e mod Er != 0, interleaved
     constexpr int NM = S::EL - S::EL / ER;
-    Fe ys[NM], ws[NM];
-    sfor<S::EL>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      constexpr int s = e % ER;
-      constexpr int k = e - e / ER - 1;  // rank among the s != 0 points
-      if constexpr (s != 0) {
-        const uint32_t im = (q + (e / ER) * S::SLOT_STRIDE) & (NSR - 1);
-        ys[k] = v[e];
-        ws[k] = tw_r[(S::R / (NSR * ER)) * s * im];
-      }
-    });
-    mul_many<F, NM, mul_group<S::EL>()>(ys, ws);
-    sfor<S::EL>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      constexpr int k = e - e / ER - 1;
-      if constexpr (e % ER != 0) v[e] = ys[k];
-    });
+    // In round 1 with wave-major slots, q mod 4 is the same on a whole wave,
+    // and the wave with q mod 4 = 0 would multiply by w^0 = 1: it skips the
+    // products (the result is the same bytes).
+    bool twiddle = true;
+    if constexpr (S::WAVE_Q && RHO == 1 && ER == 4) twiddle = __builtin_amdgcn_readfirstlane(q & 3u) != 0;
+    if (twiddle) {
+      Fe ys[NM], ws[NM];
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        constexpr int s = e % ER;
+        constexpr int k = e - e / ER - 1;  // rank among the s != 0 points
+        if constexpr (s != 0) {
+          const uint32_t im = (q + (e / ER) * S::SLOT_STRIDE) & (NSR - 1);
+          ys[k] = v[e];
+          ws[k] = tw_r[(S::R / (NSR * ER)) * s * im];
+        }
+      });
+      mul_many<F, NM, mul_group<S::EL>()>(ys, ws);
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        constexpr int k = e - e / ER - 1;
+        if constexpr (e % ER != 0) v[e] = ys[k];
+      });
+    }
   }
   Fe W[ER / 2 > 0 ? ER / 2 : 1];
   sfor<ER / 2>([&](auto k_) {
@@ -261,8 +274,17 @@ __device__ __forceinline__ void tile_round(Fe (&v)[N], Fe* lds, const Fe* __rest
 template <class F, int LOG_R, int LOG_TILE, int LOG_E>
 __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* lds, uint32_t t, bool writer) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
+  // Thread t of the tile handles column c and slot q.  Lanes of a wave take
+  // the J columns fastest (so global accesses stay in J x 32-byte runs); the
+  // slots either follow the thread index (q = t / J) or, with wave-major
+  // numbering, take the wave index as their lowest bits (q = w + WAVES k).
   const uint32_t c = t & (S::J - 1);  // column within the tile
-  const uint32_t q = t >> S::LOG_J;   // thread index within the column
+  uint32_t q;                         // slot within the column
+  if constexpr (S::WAVE_Q) {
+    q = (t >> 6) + S::WAVES * ((t & 63) >> S::LOG_J);
+  } else {
+    q = t >> S::LOG_J;
+  }
   const uint64_t n = 1ull << a.log_n;
   const uint64_t ns = 1ull << a.log_ns;
   const uint64_t j = tile * S::J + c;           // global column, < n / R
