@@ -315,18 +315,25 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
     });
     mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   } else if (a.tw_hi) {  // the same twiddle from the two-level tables
+    // Two points at a time: holding both factors of every point at once
+    // (2 EL elements on top of the data) made this branch the kernel's
+    // register peak and spilled registers in every pass, table mode included.
     const uint64_t jm = j & (ns - 1);
     const uint32_t log_mult = a.log_n - a.log_ns - LOG_R;
     const uint64_t lo_mask = (1ull << a.log_lo) - 1;
-    Fe lo[S::EL];
-    sfor<S::EL>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      const uint64_t ex = (point0(e) * jm) << log_mult;
-      w[e] = load_fe(a.tw_hi, ex >> a.log_lo);
-      lo[e] = load_fe(a.tw_lo, ex & lo_mask);
+    constexpr int CH = S::EL >= 2 ? 2 : 1;
+    sfor<S::EL / CH>([&](auto h_) {
+      constexpr int h = decltype(h_)::value;
+      Fe hi[CH], lo[CH];
+      sfor<CH>([&](auto k_) {
+        constexpr int k = decltype(k_)::value;
+        const uint64_t ex = (point0(CH * h + k) * jm) << log_mult;
+        hi[k] = load_fe(a.tw_hi, ex >> a.log_lo);
+        lo[k] = load_fe(a.tw_lo, ex & lo_mask);
+      });
+      mul_many<F, CH, CH>(hi, lo);
+      mul_many<F, CH, CH>(v + CH * h, hi);
     });
-    mul_many<F, S::EL, mul_group<S::EL>()>(w, lo);
-    mul_many<F, S::EL, mul_group<S::EL>()>(v, w);
   }
 
   if constexpr (S::ROUNDS > 0) tile_round<F, LOG_R, LOG_TILE, LOG_E, 0>(v, lds, a.tw_r, c, q, writer);
