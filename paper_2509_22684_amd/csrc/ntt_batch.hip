@@ -45,8 +45,8 @@ constexpr int kBatchLogE = 2;
 constexpr int kBatchThreads = (1 << kBatchTileLog) >> kBatchLogE;
 constexpr int kBatchLdsSlots = (1 << kBatchTileLog) + (1 << kBatchTileLog) / 8;
 constexpr int kBatchWgsPerCu = 163840 / (kBatchLdsSlots * 32);  // LDS limit
-// Products interleaved per group in the batch tile body: two keep its
-// register allocation at 128 VGPRs with 22 spilled (three: 34, four: 110).
+// Products interleaved per group in the batch tile body: two and three fit
+// 128 VGPRs without spills (four spills 28); two measured faster.
 constexpr int kDynGroup = 2;
 
 // Control words are read and written with relaxed device-scope atomics.
@@ -126,18 +126,22 @@ __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_t
     });
     detail::mul_many<F, 4, kDynGroup>(v, w);
   } else if (a.tw_hi) {
+    // two points at a time, as in pass_tile, to keep the register peak down
     const uint64_t jm = j & (ns - 1);
     const uint32_t log_mult = a.log_n - a.log_ns - log_r;
     const uint64_t lo_mask = (1ull << a.log_lo) - 1;
-    Fe lo[4];
-    sfor<4>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      const uint64_t ex = ((uint64_t)(q + e * quarter) * jm) << log_mult;
-      w[e] = load_fe(a.tw_hi, ex >> a.log_lo);
-      lo[e] = load_fe(a.tw_lo, ex & lo_mask);
+    sfor<2>([&](auto h_) {
+      constexpr int h = decltype(h_)::value;
+      Fe hi[2], lo[2];
+      sfor<2>([&](auto k_) {
+        constexpr int e = 2 * h + decltype(k_)::value;
+        const uint64_t ex = ((uint64_t)(q + e * quarter) * jm) << log_mult;
+        hi[e - 2 * h] = load_fe(a.tw_hi, ex >> a.log_lo);
+        lo[e - 2 * h] = load_fe(a.tw_lo, ex & lo_mask);
+      });
+      detail::mul_many<F, 2, 2>(hi, lo);
+      detail::mul_many<F, 2, 2>(v + 2 * h, hi);
     });
-    detail::mul_many<F, 4, kDynGroup>(w, lo);
-    detail::mul_many<F, 4, kDynGroup>(v, w);
   }
 
   const int r4 = log_r >> 1;  // radix-4 rounds
