@@ -90,6 +90,45 @@ def uniform_field_vector(field: str, n: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(out).view(np.uint32).reshape(n, 8)
 
 
+def boundary_values(field: str) -> list[int]:
+    """Values at the edges of [0, p) and of the 32-bit limbs: 0..3, p - 1 ..
+    p - 3, (p -+ 1) / 2, the largest values of 1, 2, 4 and 6 limbs, 2^32 and
+    2^64, the largest power of two below p, 2^256 mod p, and p minus 2^32,
+    2^64 and 2^128.  All are canonical (< p)."""
+    p = MODULI[field]
+    top = 1 << (p.bit_length() - 1)
+    vals = [0, 1, 2, 3, p - 1, p - 2, p - 3, (p - 1) // 2, (p + 1) // 2,
+            (1 << 32) - 1, 1 << 32, (1 << 64) - 1, 1 << 64, (1 << 128) - 1, (1 << 192) - 1,
+            top, (1 << 256) % p, p - (1 << 32), p - (1 << 64), p - (1 << 128)]
+    assert all(0 <= v < p for v in vals)
+    return vals
+
+
+def boundary_field_vector(field: str, n: int, seed: int) -> np.ndarray:
+    """n canonical elements concentrated at the edges of the range, as an
+    [n, 8] uint32 array: per element, one stream output picks the class --
+    a value from boundary_values, p - 1 - s or s with s a random number of
+    random bit length below 64, or a uniform element -- and a second one
+    picks the value within the class."""
+    p = MODULI[field]
+    vals = boundary_values(field)
+    uni = limbs_to_ints(uniform_field_vector(field, n, seed ^ 0x5EED))
+    u = splitmix_outputs(seed, 0, 2 * n).reshape(n, 2)
+    out = []
+    for i in range(n):
+        a, b = int(u[i, 0]), int(u[i, 1])
+        cls = a & 3
+        if cls == 0:
+            out.append(vals[(a >> 8) % len(vals)])
+        elif cls == 1:
+            out.append(p - 1 - (b >> ((a >> 8) & 63)))
+        elif cls == 2:
+            out.append(b >> ((a >> 8) & 63))
+        else:
+            out.append(uni[i])
+    return ints_to_limbs(out)
+
+
 def limbs_to_ints(a: np.ndarray) -> list[int]:
     """[n, 8] uint32 limbs to Python ints (no reduction, no conversion)."""
     a = np.ascontiguousarray(a, dtype=np.uint32)
