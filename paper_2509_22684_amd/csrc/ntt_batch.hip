@@ -374,24 +374,24 @@ __device__ __forceinline__ bool run_item(const QueueCtl& c, uint32_t it, Fe* lds
   }
   release_to_l2();
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(done + pass, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(c.ctl + kCtlItemsDone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(done + pass, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
-// Drain this XCD's share of queues [lo, hi), all on field F; false once the
-// error flag stops the batch.  Each field has its own loop so that each loop
-// body is register-allocated for one field's arithmetic alone.
+// Drain this XCD's share of queues [lo, hi), all on field F, counting the
+// items run in `ran`; false once the error flag stops the batch.  Each field
+// has its own loop so that each loop body is register-allocated for one
+// field's arithmetic alone.
 template <class F>
-__device__ __forceinline__ bool drain(const QueueCtl& c, uint32_t lo, uint32_t hi, Fe* lds, LoopShared* sh) {
+__device__ __forceinline__ bool drain(const QueueCtl& c, uint32_t lo, uint32_t hi, Fe* lds, LoopShared* sh,
+                                      uint32_t& ran) {
   uint32_t q = find_queue(c, lo, hi, sh);
   while (q != kNone) {
     const uint32_t k = pop(c, q, sh);
     if (k == kNone) return false;
     if (k < c.queues[q].size) {
       if (!run_item<F>(c, c.queues[q].base + k, lds, sh)) return false;
+      ++ran;
     } else {
       q = find_queue(c, lo, hi, sh);
     }
@@ -407,13 +407,18 @@ __global__ void __launch_bounds__(kBatchThreads, kBatchWgsPerCu * kBatchThreads 
   __shared__ LoopShared sh;
   const QueueCtl c{jobs, items, queues, ctl, ctl[kCtlSpinLimit],
                    (uint32_t)__builtin_amdgcn_readfirstlane(xcc_id()) + 1u};
-  if (drain<Bls12_381Fr>(c, 0, q_end0, lds, &sh) && drain<Bn254Fr>(c, q_end0, q_end1, lds, &sh))
-    drain<Bls12_377Fr>(c, q_end1, q_end2, lds, &sh);
+  // Items run by this workgroup, added to the shared count once at exit: a
+  // device-scope atomic on one word per item serialised every item of the
+  // batch behind it.
+  uint32_t ran = 0;
+  if (drain<Bls12_381Fr>(c, 0, q_end0, lds, &sh, ran) && drain<Bn254Fr>(c, q_end0, q_end1, lds, &sh, ran))
+    drain<Bls12_377Fr>(c, q_end1, q_end2, lds, &sh, ran);
 
   // The last workgroup out checks that every item ran (acquire-release on
-  // the exit count orders each workgroup's item counts before its exit).
+  // the exit count orders each workgroup's item count before its exit).
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (ran) __hip_atomic_fetch_add(ctl + kCtlItemsDone, ran, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t exited = __hip_atomic_fetch_add(ctl + kCtlExited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (exited + 1 == gridDim.x && load_relaxed(ctl + kCtlItemsDone) != nitems)
       atomicOr(ctl + kCtlError, kBatchErrIncomplete);
