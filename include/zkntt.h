@@ -74,7 +74,8 @@ typedef struct {
                                0 default (10), 10 or 11 (2^11 tiles: twice the LDS, half the
                                workgroups per CU) */
   uint32_t flags;           /* ZK_FLAG_* */
-  uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (8), 4..8 */
+  uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (9 up to
+                               n = 2^18, so at most two passes there; 8 above), 4..9 */
 } ntt_plan_opts;
 
 #define ZK_FLAG_VALIDATE 1u /* check that inputs are canonical (adds a device-to-host sync) */

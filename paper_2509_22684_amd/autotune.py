@@ -37,9 +37,9 @@ def candidates(log2n: int, batchable: bool = False) -> list[dict]:
     if log2n <= 11:
         return [dict(log2_radix=2)] if batchable else [dict(log2_radix=e) for e in (1, 2, 3)]
     if batchable:
-        return [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm) for pr in (6, 7, 8) for tm in (1, 2)]
+        return [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm) for pr in (6, 7, 8, 9) for tm in (1, 2)]
     out = [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm, log2_tile=tile)
-           for pr in (6, 7, 8) for tm in (1, 2) for tile in (11, 10)]
+           for pr in (6, 7, 8, 9) for tm in (1, 2) for tile in (11, 10)]
     if not batchable:  # radix-2 and radix-8 register rounds on the default split
         out += [dict(log2_radix=1), dict(log2_radix=3)]
     return out

@@ -398,8 +398,8 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   ntt_plan_opts o{};
   if (opts) o = *opts;
   if (o.twiddle_mode > 2) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0, 1 or 2");
-  if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 8))
-    return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..8");
+  if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 9))
+    return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..9");
   if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
   if (!(o.log2_tile == 0 || o.log2_tile == 10 || o.log2_tile == 11))
     return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 10 or 11");
@@ -413,7 +413,11 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->log_e = o.log2_radix ? (int)o.log2_radix : 2;
   p->flags = o.flags;
   p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
-  p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : 8;
+  // Default pass depth: up to 2^18 two passes of at most 2^9 points (a third
+  // pass would cost another launch or, in a batch, another round of tiles
+  // and dependency waits); above, passes of at most 2^8 points, which
+  // measured fastest at 2^24.
+  p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : (log2n <= 18 ? 9 : 8);
   p->log_tile = o.log2_tile ? o.log2_tile : 10;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {

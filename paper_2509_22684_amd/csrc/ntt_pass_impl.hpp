@@ -406,7 +406,7 @@ hipError_t launch_one(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Multi-pass tiles of 2^11 or 2^10 elements with radix 2^3 .. 2^8 per pass, and
+// Multi-pass tiles of 2^11 or 2^10 elements with radix 2^3 .. 2^9 per pass, and
 // single-pass transforms of up to 2^11 points held in one tile.  Keep in step
 // with pass_shape_supported().
 template <class F, int LOG_E>
@@ -419,6 +419,7 @@ hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_
       case 6: return launch_one<F, 6, 10, LOG_E>(a, s);
       case 7: return launch_one<F, 7, 10, LOG_E>(a, s);
       case 8: return launch_one<F, 8, 10, LOG_E>(a, s);
+      case 9: return launch_one<F, 9, 10, LOG_E>(a, s);
       default: break;
     }
   }
@@ -430,6 +431,7 @@ hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_
       case 6: return launch_one<F, 6, 11, LOG_E>(a, s);
       case 7: return launch_one<F, 7, 11, LOG_E>(a, s);
       case 8: return launch_one<F, 8, 11, LOG_E>(a, s);
+      case 9: return launch_one<F, 9, 11, LOG_E>(a, s);
       case 11: return launch_one<F, 11, 11, LOG_E>(a, s);
       default: break;
     }

@@ -37,7 +37,7 @@ def _delta0(c, n):
 
 
 @pytest.mark.parametrize("field", FIELDS)
-@pytest.mark.parametrize("log2n", [1, 2, 4, 7, 10, 11, 12, 13, 16, 17])
+@pytest.mark.parametrize("log2n", [1, 2, 4, 7, 10, 11, 12, 13, 16, 17, 18])
 def test_boundary_inputs_all_kinds(cuda, field, log2n):
     from paper_2509_22684_amd import Plan
 
@@ -72,8 +72,9 @@ def test_constant_and_one_point_vectors(cuda, field, log2n):
 
 @pytest.mark.parametrize("opts", [dict(log2_radix=1), dict(log2_radix=3), dict(log2_tile=11),
                                   dict(log2_pass_radix=4), dict(log2_pass_radix=6, twiddle_mode=2),
-                                  dict(log2_pass_radix=7, twiddle_mode=1), dict(twiddle_mode=2)])
-@pytest.mark.parametrize("log2n", [13, 16])
+                                  dict(log2_pass_radix=7, twiddle_mode=1), dict(twiddle_mode=2),
+                                  dict(log2_pass_radix=9, twiddle_mode=2)])
+@pytest.mark.parametrize("log2n", [13, 16, 18])
 def test_boundary_inputs_other_schedules(cuda, opts, log2n):
     from paper_2509_22684_amd import Plan
 
@@ -122,7 +123,7 @@ def test_boundary_batch(cuda):
 
     cases = [("bls12_381_fr", 12, "forward"), ("bls12_381_fr", 14, "inverse"), ("bn254_fr", 13, "coset_forward"),
              ("bn254_fr", 11, "coset_inverse"), ("bls12_377_fr", 15, "forward"), ("bls12_377_fr", 9, "inverse"),
-             ("bls12_381_fr", 5, "coset_forward"), ("bls12_381_fr", 17, "coset_inverse")]
+             ("bls12_381_fr", 5, "coset_forward"), ("bls12_381_fr", 17, "coset_inverse"), ("bn254_fr", 18, "forward")]
     ins = [si.boundary_field_vector(f, 1 << L, si.stream_seed(74, L, k)) for k, (f, L, _) in enumerate(cases)]
     plans = [Plan(f, L) for f, L, _ in cases]
     bufs = [to_dev(x, cuda) for x in ins]

@@ -159,6 +159,10 @@ def test_error_codes(cuda):
     with pytest.raises(ZkError) as e:
         ntt_plan_create(4, 10)  # no such field
     assert e.value.code == -2
+    for bad in (3, 10):  # pass depths without a kernel
+        with pytest.raises(ZkError) as e:
+            ntt_plan_create("bls12_381_fr", 20, log2_pass_radix=bad)
+        assert e.value.code == -2
     plan = _plan("bls12_381_fr", 14)
     buf = torch.zeros(2 * plan.n + 8, 8, dtype=torch.int32, device=cuda)
     work = torch.zeros(plan.n, 8, dtype=torch.int32, device=cuda)
@@ -188,8 +192,11 @@ def test_validate_flag_rejects_noncanonical(cuda):
                                   dict(log2_pass_radix=7, twiddle_mode=2), dict(log2_pass_radix=5),
                                   dict(log2_pass_radix=4, twiddle_mode=2), dict(log2_tile=10),
                                   dict(log2_tile=10, log2_pass_radix=7, twiddle_mode=2),
-                                  dict(log2_tile=10, log2_radix=3), dict(log2_tile=10, log2_radix=1)])
-@pytest.mark.parametrize("log2n", [11, 12, 17, 20])
+                                  dict(log2_tile=10, log2_radix=3), dict(log2_tile=10, log2_radix=1),
+                                  dict(log2_pass_radix=8), dict(log2_pass_radix=9), dict(log2_pass_radix=9, log2_tile=11),
+                                  dict(log2_pass_radix=9, twiddle_mode=2), dict(log2_pass_radix=9, log2_radix=3),
+                                  dict(log2_pass_radix=9, log2_radix=1)])
+@pytest.mark.parametrize("log2n", [11, 12, 17, 18, 20])
 def test_schedules_are_byte_identical(cuda, opts, log2n):
     """Every schedule the autotuner may pick (pass fusion depth, twiddle
     source) gives the oracle's bytes for all four transforms."""
