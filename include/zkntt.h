@@ -157,9 +157,13 @@ int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, cons
  * autotuning of such parameters); a batch deals its jobs' tiles into work
  * queues (pass-major within a queue) that a grid of persistent workgroups
  * drains.  Each queue is claimed by one XCD, so all tiles of a job run under
- * one L2.  A job larger than an eighth of the batch (in tiles) would be the
- * critical path on one XCD; it runs instead as its own pass launches over the
- * whole chip, ahead of the persistent kernel, in the same stream and graph.
+ * one L2.  Transforms of equal plans (field, size, schedule) and kind form
+ * groups; a group whose tiles fill the chip, or whose jobs would be the
+ * critical path on one XCD, runs instead as grouped pass launches (one
+ * launch per pass for all jobs of the group) over the whole chip, ahead of
+ * the persistent kernel in the same stream and graph; the choice follows a
+ * time estimate made when the batch is created.  A pointwise job larger
+ * than an eighth of the batch runs as its own launch the same way.
  * Every tile is computed exactly as in the stand-alone transform, so results
  * are byte-identical to ntt_forward.
  *
@@ -235,8 +239,8 @@ int ntt_batch_status(const ntt_batch *b);
  * dependency wait fail at once (a test hook for the error path).  Synchronous. */
 int ntt_batch_set_spin_limit(ntt_batch *b, uint32_t polls);
 
-/* Work items (tiles) the persistent kernel drains (jobs run as direct pass
- * launches are not counted) and persistent workgroups per launch. */
+/* Work items (tiles) the persistent kernel drains (jobs run as grouped or
+ * direct launches are not counted) and persistent workgroups per launch. */
 int ntt_batch_items(const ntt_batch *b);
 int ntt_batch_grid(const ntt_batch *b);
 

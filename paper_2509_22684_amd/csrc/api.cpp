@@ -19,6 +19,7 @@
 // arguments.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <algorithm>
@@ -580,21 +581,23 @@ const char* zk_last_error(void) { return g_last_error.c_str(); }
 // ---------------------------------------------------------------------------
 // Batches
 
-// A batch job run as its own launches (see batch_build).
-struct DirectJob {
+// Work of a batch run as ordinary launches ahead of the persistent kernel
+// (see batch_build): a pointwise job, or a group of transforms of one plan
+// and kind, one grouped pass launch per pass.
+struct DirectWork {
   const ntt_plan* plan;
-  Kind kind;
   bool pointwise;
-  const void* in;
+  const void* in;  // pointwise operands
   const void* in2;
   const void* in3;
   void* out;
-  void* work;
+  std::vector<zk::PassArgs> pass;  // grouped transforms
+  std::vector<size_t> ptr_off;     // per pass: offset of its in pointers in the batch's pointer array
 };
 
 struct ntt_batch {
   int device = 0;
-  std::vector<DirectJob> direct;
+  std::vector<DirectWork> direct;
   uint32_t njobs = 0;
   uint32_t nitems = 0;
   uint32_t nq_end[3] = {0, 0, 0};  // end of each field's queues: BLS12-381, BN254, BLS12-377
@@ -633,16 +636,20 @@ void free_batch(ntt_batch* b) {
 }
 
 // Everything one launch of the batch does, in stream order: the direct
-// jobs' pass launches, then the counter reset and the persistent kernel.
+// work's launches, then the counter reset and the persistent kernel.
 int batch_enqueue(const ntt_batch* b, hipStream_t s) {
-  for (const DirectJob& d : b->direct) {
+  for (const DirectWork& d : b->direct) {
     if (d.pointwise) {
       hipError_t e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in),
                                                    static_cast<const Fe*>(d.in2), static_cast<const Fe*>(d.in3),
                                                    static_cast<Fe*>(d.out), d.plan->zinv, d.plan->n, s);
       if (e != hipSuccess) return hip_fail(e, "pointwise launch");
-    } else if (int rc = run_transform(d.plan, d.kind, d.in, d.out, d.work, s)) {
-      return rc;
+      continue;
+    }
+    for (size_t q = 0; q < d.pass.size(); ++q) {
+      const PassDesc& pd = d.plan->passes[q];
+      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, d.plan->log_e, d.pass[q], s);
+      if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
     }
   }
   hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
@@ -722,9 +729,21 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       J.pass[q].tiles = (uint32_t)(p->n >> batch_tile);
     }
   }
-  // A job larger than an eighth of the batch (load = tiles over all passes)
-  // would be the critical path on one XCD: it runs as its own pass launches
-  // over the whole chip, ahead of the persistent kernel, in the same stream.
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  // Transforms of equal plans and kind form groups.  The persistent kernel
+  // keeps each job on one XCD, and its run-time-shape tile body issues at
+  // about half the rate of the pass kernels; a group that fills the chip can
+  // instead run as ordinary pass launches, one per pass for all its jobs
+  // (grouped launches), ahead of the persistent kernel in the same stream.
+  // Which groups do is chosen greedily on a time estimate, with constants
+  // measured on MI355X: the grouped launches take, per pass, a launch gap
+  // plus rounds of pass tiles over the chip; the persistent kernel takes the
+  // larger of its items spread over all its workgroups and its largest job
+  // alone on one XCD.  A group moves while that lowers the estimated total.
+  // A pointwise job runs on its own when it is more than an eighth of the
+  // batch.
   auto load = [&](int k) {
     uint64_t t = 0;
     for (uint32_t q = 0; q < jobs[k].npasses; ++q) t += jobs[k].pass[q].tiles;
@@ -732,8 +751,86 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   };
   uint64_t total = 0;
   for (int k = 0; k < njobs; ++k) total += load(k);
+  // Plans with equal field, size and schedule hold equal tables, so a group
+  // may span several such plans and run on the first one's tables.
+  std::vector<std::vector<int>> groups;  // in order of first appearance
+  {
+    auto same = [&](int a, int b) {
+      const ntt_plan* x = specs[a].plan;
+      const ntt_plan* y = specs[b].plan;
+      return kinds[a] == kinds[b] && x->field == y->field && x->log_n == y->log_n && x->log_e == y->log_e &&
+             x->max_log_r == y->max_log_r && x->log_tile == y->log_tile && x->twiddle_mode == y->twiddle_mode;
+    };
+    for (int k = 0; k < njobs; ++k) {
+      if (jobs[k].kind != zk::kJobTransform) continue;
+      size_t g = 0;
+      while (g < groups.size() && !same(groups[g][0], k)) ++g;
+      if (g == groups.size()) groups.emplace_back();
+      groups[g].push_back(k);
+    }
+  }
   std::vector<bool> direct(njobs, false);
-  for (int k = 0; k < njobs; ++k) direct[k] = load(k) * zk::kXcds > total;
+  for (int k = 0; k < njobs; ++k)
+    if (jobs[k].kind == zk::kJobPointwise) direct[k] = load(k) * zk::kXcds > total;
+  constexpr double kLaunchUs = 4.0;      // gap between dependent launches
+  constexpr double kRoundUs = 40.0;      // one round of 2^10-element pass tiles, 4 per CU
+  constexpr double kBatchItemUs = 70.0;  // one 2^11-element item of the persistent kernel
+  const double batch_slots = (double)cus * zk::batch_workgroups_per_cu();
+  const size_t G = groups.size();
+  std::vector<double> grouped_us(G), group_items(G), alone_us(G);
+  for (size_t g = 0; g < G; ++g) {
+    const ntt_plan* p = specs[groups[g][0]].plan;
+    const int log_tile = p->passes[0].log_tile;
+    const uint64_t tiles = (p->n >> log_tile) * groups[g].size();  // per pass, at the plan's tile
+    const double slots = (double)cus * (log_tile >= 11 ? 2 : 4);
+    const double round_us = kRoundUs * (double)(1u << (log_tile > 10 ? log_tile - 10 : 0));
+    grouped_us[g] = (double)p->passes.size() * (kLaunchUs + std::ceil((double)tiles / slots) * round_us);
+    group_items[g] = (double)(load(groups[g][0]) * groups[g].size());
+    alone_us[g] = (double)load(groups[g][0]) * kBatchItemUs / (batch_slots / zk::kXcds);
+  }
+  double other_items = 0, other_alone = 0;  // persistent work outside the groups
+  for (int k = 0; k < njobs; ++k)
+    if (jobs[k].kind == zk::kJobPointwise && !direct[k]) {
+      other_items += (double)load(k);
+      other_alone = std::max(other_alone, (double)load(k) * kBatchItemUs / (batch_slots / zk::kXcds));
+    }
+  std::vector<bool> moved(G, false);
+  auto estimate = [&](size_t flip) {
+    double t = 0, it = other_items, alone = other_alone;
+    for (size_t g = 0; g < G; ++g) {
+      if (moved[g] != (g == flip)) {
+        t += grouped_us[g];
+      } else {
+        it += group_items[g];
+        alone = std::max(alone, alone_us[g]);
+      }
+    }
+    return t + (it > 0 ? std::max(it * kBatchItemUs / batch_slots, alone) : 0.0);
+  };
+  for (double best = estimate(G);;) {
+    size_t pick = G;
+    for (size_t g = 0; g < G; ++g) {
+      if (moved[g]) continue;
+      const double t = estimate(g);
+      if (t < best) {
+        best = t;
+        pick = g;
+      }
+    }
+    if (pick == G) break;
+    moved[pick] = true;
+  }
+  std::vector<std::vector<int>> direct_groups;
+  for (size_t g = 0; g < G; ++g) {
+    if (!moved[g]) continue;
+    const ntt_plan* p = specs[groups[g][0]].plan;
+    // one launch holds at most 2^31 workgroups
+    const size_t per_launch = std::max<size_t>(1, (1ull << 31) / (p->n >> p->passes[0].log_tile));
+    for (size_t i = 0; i < groups[g].size(); i += per_launch)
+      direct_groups.emplace_back(groups[g].begin() + i,
+                                 groups[g].begin() + std::min(groups[g].size(), i + per_launch));
+    for (int k : groups[g]) direct[k] = true;
+  }
 
   // Work queues of the other jobs.  Per field, jobs are dealt largest first
   // to the least loaded of up to queues_per_field queues; queues are listed
@@ -780,24 +877,38 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->njobs = (uint32_t)njobs;
   b->nitems = (uint32_t)items.size();
   for (int fi = 0; fi < 3; ++fi) b->nq_end[fi] = nq_end[fi];
+  // Direct work; the grouped launches' per-job vector pointers go to one
+  // device array, `ptrs`, in and out lists for each pass of each group.
+  std::vector<uintptr_t> ptrs;
   for (int k = 0; k < njobs; ++k)
-    if (direct[k]) {
+    if (direct[k] && jobs[k].kind == zk::kJobPointwise) {
       const ntt_batch_job& sp = specs[k];
-      b->direct.push_back(DirectJob{sp.plan, kinds[k], sp.op == ZK_OP_QUOTIENT_POINTWISE, sp.in, sp.in2, sp.in3,
-                                    sp.out, sp.work});
+      b->direct.push_back(DirectWork{sp.plan, true, sp.in, sp.in2, sp.in3, sp.out, {}, {}});
     }
-  int cus = 0;
-  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) {
-    free_batch(b);
-    return hip_fail(e, "hipDeviceGetAttribute");
+  for (const std::vector<int>& g : direct_groups) {
+    const ntt_plan* p = specs[g[0]].plan;
+    DirectWork d{p, false, nullptr, nullptr, nullptr, nullptr, {}, {}};
+    for (size_t q = 0; q < p->passes.size(); ++q) {
+      const ntt_batch_job& s0 = specs[g[0]];
+      zk::PassArgs a = make_pass_args(p, kinds[g[0]], q, s0.in, s0.out, s0.work);
+      a.grp_jobs = (uint32_t)g.size();
+      a.log_grp_tiles = p->log_n - (uint32_t)p->passes[q].log_tile;
+      d.ptr_off.push_back(ptrs.size());
+      for (int k : g)
+        ptrs.push_back(reinterpret_cast<uintptr_t>(make_pass_args(p, kinds[k], q, specs[k].in, specs[k].out, specs[k].work).in));
+      for (int k : g)
+        ptrs.push_back(reinterpret_cast<uintptr_t>(make_pass_args(p, kinds[k], q, specs[k].in, specs[k].out, specs[k].work).out));
+      d.pass.push_back(a);
+    }
+    b->direct.push_back(std::move(d));
   }
   b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * zk::batch_workgroups_per_cu());
   const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
   const size_t items_bytes = ((sizeof(zk::BatchItem) * items.size() + 255) / 256) * 256;
   const size_t queues_bytes = ((sizeof(zk::BatchQueue) * queues.size() + 255) / 256) * 256;
   const size_t ctl_words = zk::kCtlDone + (size_t)njobs * zk::kMaxBatchPasses;
-  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + queues_bytes + ctl_words * sizeof(uint32_t));
+  const size_t ctl_bytes = ((ctl_words * sizeof(uint32_t) + 255) / 256) * 256;
+  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t));
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "hipMalloc(batch)");
@@ -807,6 +918,12 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   b->d_items = reinterpret_cast<zk::BatchItem*>(base + jobs_bytes);
   b->d_queues = reinterpret_cast<zk::BatchQueue*>(base + jobs_bytes + items_bytes);
   b->d_ctl = reinterpret_cast<uint32_t*>(base + jobs_bytes + items_bytes + queues_bytes);
+  uintptr_t* d_ptrs = reinterpret_cast<uintptr_t*>(base + jobs_bytes + items_bytes + queues_bytes + ctl_bytes);
+  for (DirectWork& d : b->direct)
+    for (size_t q = 0; q < d.pass.size(); ++q) {
+      d.pass[q].grp_in = reinterpret_cast<const Fe* const*>(d_ptrs + d.ptr_off[q]);
+      d.pass[q].grp_out = reinterpret_cast<Fe* const*>(d_ptrs + d.ptr_off[q] + d.pass[q].grp_jobs);
+    }
   std::vector<uint32_t> ctl(ctl_words, 0);
   ctl[zk::kCtlSpinLimit] = kDefaultSpinLimit;
   if (!jobs.empty()) e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(zk::BatchJob) * jobs.size(), hipMemcpyHostToDevice);
@@ -815,6 +932,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   if (e == hipSuccess && !queues.empty())
     e = hipMemcpy(b->d_queues, queues.data(), sizeof(zk::BatchQueue) * queues.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_ctl, ctl.data(), ctl_words * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !ptrs.empty())
+    e = hipMemcpy(d_ptrs, ptrs.data(), ptrs.size() * sizeof(uintptr_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "hipMemcpy(batch descriptors)");

@@ -42,6 +42,14 @@ struct PassArgs {
   uint32_t log_ns;
   uint32_t flags;
   uint32_t log_lo;
+  // Grouped launch (grp_jobs > 0): one launch runs this pass for grp_jobs
+  // transforms of one plan, 2^log_grp_tiles tiles each; workgroup b takes
+  // tile b mod 2^log_grp_tiles of job b / 2^log_grp_tiles, reading
+  // grp_in[job] and writing grp_out[job] in place of in and out.
+  const Fe* const* grp_in;
+  Fe* const* grp_out;
+  uint32_t grp_jobs;
+  uint32_t log_grp_tiles;
 };
 
 // Shapes the pass kernels are instantiated for: tiles of 2^10 or 2^11

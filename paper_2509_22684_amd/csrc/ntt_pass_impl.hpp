@@ -389,7 +389,14 @@ __global__ void __launch_bounds__((PassShape<LOG_R, LOG_TILE, LOG_E>::THREADS),
     ntt_pass_kernel(PassArgs a) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
   __shared__ Fe lds[S::LDS_SLOTS];
-  pass_tile<F, LOG_R, LOG_TILE, LOG_E>(a, blockIdx.x, lds, threadIdx.x, true);
+  uint32_t tile = blockIdx.x;
+  if (a.grp_jobs) {
+    const uint32_t job = blockIdx.x >> a.log_grp_tiles;
+    tile = blockIdx.x & ((1u << a.log_grp_tiles) - 1u);
+    a.in = a.grp_in[job];
+    a.out = a.grp_out[job];
+  }
+  pass_tile<F, LOG_R, LOG_TILE, LOG_E>(a, tile, lds, threadIdx.x, true);
 }
 
 }  // namespace detail
@@ -401,7 +408,7 @@ namespace detail {
 template <class F, int LOG_R, int LOG_TILE, int LOG_E>
 hipError_t launch_one(const PassArgs& a, hipStream_t s) {
   using S = PassShape<LOG_R, LOG_TILE, LOG_E>;
-  const uint64_t tiles = (1ull << a.log_n) >> LOG_TILE;
+  const uint64_t tiles = ((1ull << a.log_n) >> LOG_TILE) * (a.grp_jobs ? a.grp_jobs : 1u);
   hipLaunchKernelGGL((ntt_pass_kernel<F, LOG_R, LOG_TILE, LOG_E>), dim3((uint32_t)tiles), dim3(S::THREADS), 0, s, a);
   return hipGetLastError();
 }

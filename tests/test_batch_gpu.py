@@ -306,3 +306,68 @@ def test_empty_batch(cuda):
     torch.cuda.synchronize()
     assert ntt_batch_status(h) == 0
     ntt_batch_destroy(h)
+
+
+@pytest.mark.parametrize("log2n", [17, 19])
+def test_batch_grouped_launches_every_kind(cuda, log2n):
+    """Transforms of equal plans and kind form groups; a group that fills the
+    chip runs as one grouped launch per pass (workgroup b of a launch takes a
+    tile of job b / tiles-per-job).  Every kind, in place and
+    out of place, with two plans built separately for the same size, next to
+    small jobs in the persistent kernel: all equal the oracle on two graph
+    replays, and the grouped jobs leave the persistent kernel's queues."""
+    import torch
+
+    from oracle import ref
+    from paper_2509_22684_amd import Plan, ntt_batch_create_jobs, ntt_batch_destroy, ntt_batch_launch, \
+        ntt_batch_status, lib
+
+    field = "bls12_381_fr"
+    n = 1 << log2n
+    plan_a, plan_b = Plan(field, log2n), Plan(field, log2n)  # equal schedules, separate tables
+    kinds = ["forward", "inverse", "coset_forward", "coset_inverse", "inverse_to_coset"]
+    jobs, checks = [], []
+    for k, kind in enumerate(kinds):
+        for m in range(8):  # eight jobs of 2^17 fill one round of pass tiles over the chip
+            x = si.uniform_field_vector(field, n, si.stream_seed(81, log2n, 8 * k + m))
+            plan = plan_a if m != 1 else plan_b
+            src = to_dev(x, cuda)
+            dst = src if m == 0 else torch.empty_like(src)  # job 0 of each kind in place
+            work = torch.empty_like(src)
+            jobs.append(dict(plan=plan, op=kind, out=dst, work=work, **{"in": src}))
+            checks.append((kind, x, dst))
+    small = [("bn254_fr", 10), ("bls12_381_fr", 12), ("bls12_377_fr", 11)]
+    small_plans = [Plan(f, L) for f, L in small]
+    small_in = [si.uniform_field_vector(f, 1 << L, si.stream_seed(82, L, i)) for i, (f, L) in enumerate(small)]
+    small_bufs = [to_dev(x, cuda) for x in small_in]
+    for p, b in zip(small_plans, small_bufs):
+        jobs.append(dict(plan=p, op="forward", out=b, work=p.workspace(b), **{"in": b}))
+    h = ntt_batch_create_jobs(jobs, graph=True)
+    # only the small jobs' tiles stay in the persistent kernel's queues (the
+    # batch tile holds min(n, 2^11) elements)
+    from paper_2509_22684_amd import ntt_plan_passes
+
+    small_items = sum(ntt_plan_passes(p.handle) * max(1, (1 << L) >> 11) for p, (_, L) in zip(small_plans, small))
+    assert lib().ntt_batch_items(h) == small_items
+    F = ref.FIELDS[field]
+    gpow = [pow(F.generator, j, F.p) for j in range(n)]
+    want = []
+    for kind, x, _ in checks:
+        if kind == "inverse_to_coset":
+            inv = si.limbs_to_ints(coracle.transform(field, "inverse", x))
+            want.append(si.ints_to_limbs([v * g % F.p for v, g in zip(inv, gpow)]))
+        else:
+            want.append(coracle.transform(field, kind, x))
+    small_want = [coracle.transform(f, "forward", x) for (f, _), x in zip(small, small_in)]
+    for rep in range(2):
+        for (kind, x, dst), job in zip(checks, jobs):
+            job["in"].copy_(torch.from_numpy(x.view(np.int32)))
+        for b, x in zip(small_bufs, small_in):
+            b.copy_(torch.from_numpy(x.view(np.int32)))
+        ntt_batch_launch(h)
+        torch.cuda.synchronize()
+        assert ntt_batch_status(h) == 0
+        for (kind, _, dst), w in zip(checks, want):
+            assert np.array_equal(to_host(dst), w), f"grouped {kind} 2^{log2n} launch {rep}"
+        _check_all(small_bufs, small_want, f"small jobs beside groups, launch {rep}")
+    ntt_batch_destroy(h)
