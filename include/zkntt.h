@@ -69,7 +69,8 @@ typedef enum {
 typedef struct {
   uint32_t twiddle_mode;    /* 0 default; 1 one precomputed table per pass in HBM;
                                2 two small tables and one extra multiplication per element */
-  uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (2), 1 (radix-2), 2 or 3 */
+  uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (1, radix-2, up to
+                               n = 2^18; 2 above), 1 (radix-2), 2 or 3 */
   uint32_t log2_tile;       /* elements per workgroup tile of a multi-pass transform, log2:
                                0 default (10), 10 or 11 (2^11 tiles: twice the LDS, half the
                                workgroups per CU) */

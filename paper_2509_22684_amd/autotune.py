@@ -69,8 +69,42 @@ def time_forward(plan, x, out, reps: int) -> float:
     return statistics.median(ms)
 
 
+def batch_jobs_for(log2n: int) -> int:
+    """Jobs of one size in the batch a batchable schedule is timed in: about
+    2^20 elements in all, 1 to 64 jobs."""
+    return max(1, min(64, (1 << 20) >> log2n))
+
+
+def time_batched(plan, bufs, reps: int) -> float:
+    """Median time of one graph replay of an in-place forward batch over
+    `bufs`, all with `plan`: the schedule as the batch runs it (its tiles,
+    pass split and choice of grouped launches)."""
+    import torch
+
+    from ._lib import Batch
+
+    batch = Batch([plan] * len(bufs), bufs)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        batch.launch(stream)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batch.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    if batch.status() != 0:
+        raise RuntimeError(f"batch status {batch.status()} while tuning")
+    batch.close()
+    return statistics.median(ms)
+
+
 def tune(field: str, log2n: int, reps: int = 5, batchable: bool = False) -> dict:
-    """Time every candidate; return {"opts": best, "ms": t, "candidates": [...]}"""
+    """Time every candidate; return {"opts": best, "ms": t, "candidates": [...]}.
+    Stand-alone schedules are timed as one forward NTT; batchable ones inside
+    a batch of batch_jobs_for(log2n) equal jobs."""
     import numpy as np
     import torch
 
@@ -82,13 +116,15 @@ def tune(field: str, log2n: int, reps: int = 5, batchable: bool = False) -> dict
     host = si.uniform_field_vector(field, n, si.stream_seed(77, log2n, 0))
     x = torch.from_numpy(host.view(np.int32)).cuda()
     out = torch.empty_like(x)
+    bufs = [x.clone() for _ in range(batch_jobs_for(log2n))] if batchable else []
     rows = []
     for opts in candidates(log2n, batchable):
         try:
             plan = Plan(field, log2n, **opts)
         except ZkError:
             continue
-        rows.append({"opts": opts, "ms": time_forward(plan, x, out, reps), "passes": plan.passes})
+        ms = time_batched(plan, bufs, reps) if batchable else time_forward(plan, x, out, reps)
+        rows.append({"opts": opts, "ms": ms, "passes": plan.passes})
         plan.close()
     best = min(rows, key=lambda r: r["ms"])
     return {"opts": best["opts"], "ms": best["ms"], "candidates": rows}

@@ -411,7 +411,11 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->field = field;
   p->log_n = log2n;
   p->n = 1ull << log2n;
-  p->log_e = o.log2_radix ? (int)o.log2_radix : 2;
+  // Default register radix: radix-2 rounds (two elements per thread, twice
+  // the threads per tile) up to 2^18, where a transform has too few tiles to
+  // fill the chip and more waves per tile shorten each pass; radix-4 above,
+  // where every CU is busy and fewer instructions per element win.
+  p->log_e = o.log2_radix ? (int)o.log2_radix : (log2n <= 18 ? 1 : 2);
   p->flags = o.flags;
   p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
   // Default pass depth: up to 2^18 two passes of at most 2^9 points (a third
@@ -648,7 +652,7 @@ int batch_enqueue(const ntt_batch* b, hipStream_t s) {
     }
     for (size_t q = 0; q < d.pass.size(); ++q) {
       const PassDesc& pd = d.plan->passes[q];
-      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, d.plan->log_e, d.pass[q], s);
+      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, 2, d.pass[q], s);
       if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
     }
   }
@@ -751,14 +755,16 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   };
   uint64_t total = 0;
   for (int k = 0; k < njobs; ++k) total += load(k);
-  // Plans with equal field, size and schedule hold equal tables, so a group
-  // may span several such plans and run on the first one's tables.
+  // Plans with equal field, size and pass schedule hold equal tables, so a
+  // group may span several such plans and run on the first one's tables.
+  // Grouped launches fill the chip, so they use radix-4 register rounds
+  // whatever the plans' register radix (the tables and bytes are the same).
   std::vector<std::vector<int>> groups;  // in order of first appearance
   {
     auto same = [&](int a, int b) {
       const ntt_plan* x = specs[a].plan;
       const ntt_plan* y = specs[b].plan;
-      return kinds[a] == kinds[b] && x->field == y->field && x->log_n == y->log_n && x->log_e == y->log_e &&
+      return kinds[a] == kinds[b] && x->field == y->field && x->log_n == y->log_n &&
              x->max_log_r == y->max_log_r && x->log_tile == y->log_tile && x->twiddle_mode == y->twiddle_mode;
     };
     for (int k = 0; k < njobs; ++k) {
