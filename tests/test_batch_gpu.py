@@ -371,3 +371,28 @@ def test_batch_grouped_launches_every_kind(cuda, log2n):
             assert np.array_equal(to_host(dst), w), f"grouped {kind} 2^{log2n} launch {rep}"
         _check_all(small_bufs, small_want, f"small jobs beside groups, launch {rep}")
     ntt_batch_destroy(h)
+
+
+@pytest.mark.parametrize("opts", [dict(twiddle_mode=2), dict(log2_pass_radix=6), dict(log2_radix=3),
+                                  dict(log2_radix=1), dict(log2_pass_radix=7, twiddle_mode=2)])
+def test_batch_grouped_launches_other_schedules(cuda, opts):
+    """Grouped launches run the plans' pass split, tile and twiddle source
+    with radix-4 register rounds whatever the plans' register radix; eight
+    2^17 jobs of one schedule form a group that fills the chip, and every job
+    equals the oracle."""
+    import torch
+
+    from paper_2509_22684_amd import Batch, Plan, lib
+
+    field, log2n = "bn254_fr", 17
+    plan = Plan(field, log2n, **opts)
+    ins = [si.uniform_field_vector(field, 1 << log2n, si.stream_seed(83, log2n, k)) for k in range(8)]
+    want = [coracle.transform(field, "forward", x) for x in ins]
+    bufs = _fresh_bufs(ins, cuda)
+    batch = Batch([plan] * len(bufs), bufs)
+    assert lib().ntt_batch_items(batch.handle) == 0  # the whole group runs as grouped launches
+    batch.launch()
+    torch.cuda.synchronize()
+    assert batch.status() == 0
+    _check_all(bufs, want, f"grouped {opts}")
+    batch.close()
