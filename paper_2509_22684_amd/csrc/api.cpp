@@ -612,6 +612,11 @@ struct ntt_batch {
   zk::BatchQueue* d_queues = nullptr;
   uint32_t* d_ctl = nullptr;
   hipStream_t capture_stream = nullptr;
+  // with both direct work and queued items: a second stream for the direct
+  // work, forked from and joined back into the launch stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -635,30 +640,48 @@ void free_batch(ntt_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
   if (b->d_mem) (void)hipFree(b->d_mem);
   delete b;
 }
 
-// Everything one launch of the batch does, in stream order: the direct
-// work's launches, then the counter reset and the persistent kernel.
+// Everything one launch of the batch does: the counter reset and the
+// persistent kernel on s and, when the batch has direct work too, that work
+// on the side stream, forked from s before and joined into s after, so the
+// two run at the same time (the persistent grid then leaves room for it).
 int batch_enqueue(const ntt_batch* b, hipStream_t s) {
+  hipStream_t ds = s;
+  if (b->side) {
+    hipError_t e = hipEventRecord(b->fork_ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork_ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch fork");
+    ds = b->side;
+  }
+  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
+                                  b->grid, s);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
   for (const DirectWork& d : b->direct) {
     if (d.pointwise) {
       hipError_t e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in),
                                                    static_cast<const Fe*>(d.in2), static_cast<const Fe*>(d.in3),
-                                                   static_cast<Fe*>(d.out), d.plan->zinv, d.plan->n, s);
+                                                   static_cast<Fe*>(d.out), d.plan->zinv, d.plan->n, ds);
       if (e != hipSuccess) return hip_fail(e, "pointwise launch");
       continue;
     }
     for (size_t q = 0; q < d.pass.size(); ++q) {
       const PassDesc& pd = d.plan->passes[q];
-      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, 2, d.pass[q], s);
+      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, 2, d.pass[q], ds);
       if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
     }
   }
-  hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
-                                  b->grid, s);
-  return e == hipSuccess ? ZK_OK : hip_fail(e, "batch launch");
+  if (b->side) {
+    e = hipEventRecord(b->join_ev, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join_ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch join");
+  }
+  return ZK_OK;
 }
 
 bool op_to_kind(int op, Kind* k) {
@@ -908,7 +931,19 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     }
     b->direct.push_back(std::move(d));
   }
-  b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * zk::batch_workgroups_per_cu());
+  // Next to direct work the persistent kernel takes one workgroup per CU,
+  // leaving LDS and wave slots for the pass kernels beside it.
+  const bool beside = !b->direct.empty() && !items.empty();
+  b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * (beside ? 1 : zk::batch_workgroups_per_cu()));
+  if (beside) {
+    e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e, "batch side stream");
+    }
+  }
   const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
   const size_t items_bytes = ((sizeof(zk::BatchItem) * items.size() + 255) / 256) * 256;
   const size_t queues_bytes = ((sizeof(zk::BatchQueue) * queues.size() + 255) / 256) * 256;
