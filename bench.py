@@ -353,9 +353,10 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the host-resident pipeline leg")
-    ap.add_argument("--only", choices=["forward", "copy"], default=None,
-                    help="for counter runs: only run --steps forward NTTs at 2^24, or --steps plain device "
-                         "copies of one 512 MiB vector (the traffic calibration kernel), then exit")
+    ap.add_argument("--only", choices=["forward", "copy", "batch"], default=None,
+                    help="for profiler runs: only run --steps forward NTTs at 2^24, --steps plain device "
+                         "copies of one 512 MiB vector (the traffic calibration kernel), or --warmup + --steps "
+                         "graph replays of the 64-job batch, then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -381,6 +382,34 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(f"[bench] {args.steps} copies of {n * 32} bytes done", file=sys.stderr, flush=True)
+        return 0
+    if args.only == "batch":
+        # the 64-job batch as batch_leg builds it, replayed from its graph
+        from paper_2509_22684_amd import Batch
+        from paper_2509_22684_amd.autotune import tuned_opts
+
+        jobs = si.batch_jobs()
+        plans = {}
+        for jb in jobs:
+            if (jb.field, jb.log2n) not in plans:
+                plans[(jb.field, jb.log2n)] = Plan(jb.field, jb.log2n,
+                                                   **tuned_opts(jb.field, jb.log2n, batchable=True))
+        bufs = [to_dev(si.uniform_field_vector(jb.field, 1 << jb.log2n, jb.seed)) for jb in jobs]
+        batch = Batch([plans[(j.field, j.log2n)] for j in jobs], bufs)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(args.warmup):
+            batch.launch(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            batch.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"batch_ms_mean": e0.elapsed_time(e1) / max(1, args.steps), "items": batch.items,
+                          "workgroups": batch.grid, "status": batch.status(), "warmup": args.warmup,
+                          "steps": args.steps}), flush=True)
+        print(f"[bench] {args.warmup}+{args.steps} batch replays done", file=sys.stderr, flush=True)
         return 0
     if args.only == "forward":
         # --warmup untimed forwards (clocks settle), then --steps forwards
