@@ -597,6 +597,7 @@ struct DirectWork {
   void* out;
   std::vector<zk::PassArgs> pass;  // grouped transforms
   std::vector<size_t> ptr_off;     // per pass: offset of its in pointers in the batch's pointer array
+  size_t lane = 0;                 // side stream it runs on
 };
 
 struct ntt_batch {
@@ -612,11 +613,11 @@ struct ntt_batch {
   zk::BatchQueue* d_queues = nullptr;
   uint32_t* d_ctl = nullptr;
   hipStream_t capture_stream = nullptr;
-  // with both direct work and queued items: a second stream for the direct
-  // work, forked from and joined back into the launch stream
-  hipStream_t side = nullptr;
+  // side streams for the direct work, forked from and joined back into the
+  // launch stream (none when the launch stream alone has all the work)
+  std::vector<hipStream_t> sides;
+  std::vector<hipEvent_t> joins;
   hipEvent_t fork_ev = nullptr;
-  hipEvent_t join_ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -640,29 +641,31 @@ void free_batch(ntt_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-  if (b->side) (void)hipStreamDestroy(b->side);
+  for (hipStream_t x : b->sides)
+    if (x) (void)hipStreamDestroy(x);
+  for (hipEvent_t x : b->joins)
+    if (x) (void)hipEventDestroy(x);
   if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
-  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
   if (b->d_mem) (void)hipFree(b->d_mem);
   delete b;
 }
 
 // Everything one launch of the batch does: the counter reset and the
-// persistent kernel on s and, when the batch has direct work too, that work
-// on the side stream, forked from s before and joined into s after, so the
-// two run at the same time (the persistent grid then leaves room for it).
+// persistent kernel on s and the direct work on side streams, forked from s
+// before and joined into s after, so that they all run at the same time
+// (the persistent grid then leaves room for the pass kernels).
 int batch_enqueue(const ntt_batch* b, hipStream_t s) {
-  hipStream_t ds = s;
-  if (b->side) {
+  if (!b->sides.empty()) {
     hipError_t e = hipEventRecord(b->fork_ev, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork_ev, 0);
+    for (hipStream_t x : b->sides)
+      if (e == hipSuccess) e = hipStreamWaitEvent(x, b->fork_ev, 0);
     if (e != hipSuccess) return hip_fail(e, "batch fork");
-    ds = b->side;
   }
   hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
                                   b->grid, s);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
   for (const DirectWork& d : b->direct) {
+    hipStream_t ds = b->sides.empty() ? s : b->sides[d.lane];
     if (d.pointwise) {
       hipError_t e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in),
                                                    static_cast<const Fe*>(d.in2), static_cast<const Fe*>(d.in3),
@@ -676,9 +679,9 @@ int batch_enqueue(const ntt_batch* b, hipStream_t s) {
       if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
     }
   }
-  if (b->side) {
-    e = hipEventRecord(b->join_ev, b->side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join_ev, 0);
+  for (size_t i = 0; i < b->sides.size(); ++i) {
+    e = hipEventRecord(b->joins[i], b->sides[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[i], 0);
     if (e != hipSuccess) return hip_fail(e, "batch join");
   }
   return ZK_OK;
@@ -935,13 +938,36 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   // leaving LDS and wave slots for the pass kernels beside it.
   const bool beside = !b->direct.empty() && !items.empty();
   b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * (beside ? 1 : zk::batch_workgroups_per_cu()));
-  if (beside) {
-    e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming);
+  // Direct work goes to up to kSideStreams side streams, dealt largest first
+  // (by tiles over all passes) to the least loaded, so that groups too small
+  // to fill the chip alone run at the same time.
+  constexpr size_t kSideStreams = 3;
+  const size_t nsides = std::min(kSideStreams, b->direct.size());
+  if (nsides > 1 || beside) {
+    std::vector<size_t> order(b->direct.size());
+    std::vector<uint64_t> work(b->direct.size(), 0), lane_load(nsides, 0);
+    for (size_t i = 0; i < order.size(); ++i) {
+      order[i] = i;
+      const DirectWork& d = b->direct[i];
+      work[i] = d.pointwise ? (d.plan->n >> 10) : (d.plan->n >> d.plan->passes[0].log_tile) * d.pass.size() *
+                                                       std::max<uint32_t>(1, d.pass.empty() ? 1 : d.pass[0].grp_jobs);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work[a] > work[c]; });
+    for (size_t i : order) {
+      const size_t l = (size_t)(std::min_element(lane_load.begin(), lane_load.end()) - lane_load.begin());
+      b->direct[i].lane = l;
+      lane_load[l] += work[i];
+    }
+    b->sides.assign(nsides, nullptr);
+    b->joins.assign(nsides, nullptr);
+    e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+    for (size_t i = 0; i < nsides && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&b->sides[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
       free_batch(b);
-      return hip_fail(e, "batch side stream");
+      return hip_fail(e, "batch side streams");
     }
   }
   const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
