@@ -161,10 +161,13 @@ int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, cons
  * one L2.  Transforms of equal plans (field, size, schedule) and kind form
  * groups; a group whose tiles fill the chip, or whose jobs would be the
  * critical path on one XCD, runs instead as grouped pass launches (one
- * launch per pass for all jobs of the group) over the whole chip, ahead of
- * the persistent kernel in the same stream and graph; the choice follows a
- * time estimate made when the batch is created.  A pointwise job larger
- * than an eighth of the batch runs as its own launch the same way.
+ * launch per pass for all jobs of the group) over the whole chip; the choice
+ * follows a time estimate made when the batch is created.  A pointwise job
+ * larger than an eighth of the batch runs as its own launch the same way.
+ * Such launches go to up to three side streams of the batch, forked from the
+ * launch stream before the persistent kernel and joined into it after (in
+ * the graph: parallel branches), so the call still completes in stream
+ * order on the stream it was given.
  * Every tile is computed exactly as in the stand-alone transform, so results
  * are byte-identical to ntt_forward.
  *
