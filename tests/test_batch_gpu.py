@@ -234,9 +234,9 @@ def test_batch_queue_counts(c4, cuda, queues):
     [("bn254_fr", 18), ("bn254_fr", 18), ("bls12_381_fr", 10)],
 ])
 def test_batch_large_jobs_run_direct(cuda, cases):
-    """Jobs larger than an eighth of the batch run as their own pass
-    launches ahead of the persistent kernel, next to XCD-local jobs; all equal
-    the oracle, on two graph replays."""
+    """Jobs that would be the critical path on one XCD run as grouped pass
+    launches on side streams, beside the persistent kernel's XCD-local jobs;
+    all equal the oracle, on two graph replays."""
     import torch
 
     from paper_2509_22684_amd import Batch, Plan

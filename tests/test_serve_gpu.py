@@ -65,9 +65,9 @@ def test_staggered_arrivals_and_tight_budget(cuda):
 
 @pytest.mark.slow
 def test_serving_sizes_up_to_2_22(cuda):
-    """The serving size range at its ends: a 2^22 job (a stage of it larger
-    than an eighth of the tick runs as direct pass launches) beside small
-    ones; every H equals the oracle's quotient in full."""
+    """The serving size range at its ends: a 2^22 job (its stages run as
+    grouped pass launches) beside small ones; every H equals the oracle's
+    quotient in full."""
     from paper_2509_22684_amd.serve import GpuExecutor, QuotientServer
 
     reqs = _requests([22, 14, 18, 14])
