@@ -110,7 +110,9 @@ int ntt_coset_forward(const ntt_plan *p, const void *d_in, void *d_out, void *d_
  * out_j = g^-j n^-1 sum_i in_i w^(-i j). */
 int ntt_coset_inverse(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
 
-/* Bytes of device workspace quotient_poly needs. */
+/* Bytes of device workspace quotient_poly needs (up to n = 2^22 it holds
+ * three transform workspaces, so that A's and B's transforms can run at the
+ * same time as C's). */
 size_t quotient_workspace_bytes(const ntt_plan *p);
 
 /* Groth16 quotient chain (Section II, Fig. 3; seven NTTs, Section IV-A).
@@ -120,7 +122,11 @@ size_t quotient_workspace_bytes(const ntt_plan *p);
  * (Z_H(x) = x^n - 1 takes the constant value g^n - 1 on the coset) and
  * returns in H the n coefficients of the polynomial with those coset values:
  *   H = cosetINTT( (cosetNTT(INTT A) . cosetNTT(INTT B) - cosetNTT(INTT C)) / (g^n - 1) ).
- * A, B, C are not modified; H must not overlap them or d_work. */
+ * A, B, C are not modified; H must not overlap them or d_work.
+ * Up to n = 2^22 the transforms of A and B run on two streams of the plan,
+ * forked from `stream` and joined back into it before C's forward NTT, so
+ * the call still completes in the order of `stream`; calls on one plan from
+ * several threads are serialised while they enqueue. */
 int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_H,
                   void *d_work, void *stream);
 

@@ -85,6 +85,12 @@ struct ntt_plan {
   Fe* inv_to_coset = nullptr;     // n^-1 g^k
   uint32_t* d_count = nullptr;    // validation counter
   std::mutex validate_mu;
+  // quotient_poly up to 2^kQuotientForkMaxLog: A's and B's chains run on two
+  // side streams forked from the caller's stream and joined back
+  hipStream_t qside[2] = {nullptr, nullptr};
+  hipEvent_t qfork = nullptr;
+  hipEvent_t qjoin[2] = {nullptr, nullptr};
+  std::mutex quotient_mu;  // one fork/join sequence at a time per plan
 };
 
 namespace {
@@ -155,9 +161,18 @@ struct TableBuilder {
 
 void free_plan(ntt_plan* p) {
   if (!p) return;
+  for (int i = 0; i < 2; ++i) {
+    if (p->qside[i]) (void)hipStreamDestroy(p->qside[i]);
+    if (p->qjoin[i]) (void)hipEventDestroy(p->qjoin[i]);
+  }
+  if (p->qfork) (void)hipEventDestroy(p->qfork);
   for (void* d : p->owned) (void)hipFree(d);
   delete p;
 }
+
+// Plans whose quotient chain runs A's and B's transforms on side streams.
+constexpr uint32_t kQuotientForkMaxLog = 22;
+bool quotient_forks(const ntt_plan* p) { return p->log_n <= kQuotientForkMaxLog; }
 
 // Split log_n into passes of at most max_log_r stages each, larger radices
 // first (a single pass covers n up to the tile size in one tile).
@@ -436,6 +451,17 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
     free_plan(p);
     return rc;
   }
+  if (quotient_forks(p)) {
+    e = hipEventCreateWithFlags(&p->qfork, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&p->qside[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->qjoin[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "quotient side streams");
+    }
+  }
   *out = p;
   return ZK_OK;
 }
@@ -465,7 +491,7 @@ int ntt_coset_inverse(const ntt_plan* p, const void* d_in, void* d_out, void* d_
 }
 
 size_t quotient_workspace_bytes(const ntt_plan* p) {
-  return p ? (2 * p->n + workspace_elems(p)) * sizeof(Fe) : 0;
+  return p ? (2 * p->n + (quotient_forks(p) ? 3 : 1) * workspace_elems(p)) * sizeof(Fe) : 0;
 }
 
 int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_H, void* d_work,
@@ -484,8 +510,33 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
   }
   Fe* t1 = static_cast<Fe*>(d_work);
   Fe* t2 = t1 + p->n;
-  Fe* w = workspace_elems(p) ? t2 + p->n : nullptr;
+  const size_t ws = workspace_elems(p);
+  Fe* w = ws ? t2 + p->n : nullptr;
   Fe* H = static_cast<Fe*>(d_H);
+  if (quotient_forks(p)) {
+    // Up to 2^kQuotientForkMaxLog one transform does not fill the chip: A's
+    // and B's INTT->NTT chains run on two side streams beside C's INTT, each
+    // with its own workspace, and C's forward NTT with the pointwise step
+    // waits for both.  Same kernels and arguments, so the same bytes.
+    std::lock_guard<std::mutex> lock(const_cast<ntt_plan*>(p)->quotient_mu);
+    hipError_t e = hipEventRecord(p->qfork, s);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->qside[i], p->qfork, 0);
+    if (e != hipSuccess) return hip_fail(e, "quotient fork");
+    const void* src[2] = {d_A, d_B};
+    Fe* dst[2] = {t1, t2};
+    for (int i = 0; i < 2; ++i) {
+      Fe* wi = ws ? w + (size_t)(i + 1) * ws : nullptr;
+      if (int rc = run_transform(p, kInverseToCoset, src[i], dst[i], wi, p->qside[i])) return rc;
+      if (int rc = run_transform(p, kForward, dst[i], dst[i], wi, p->qside[i])) return rc;
+      e = hipEventRecord(p->qjoin[i], p->qside[i]);
+      if (e != hipSuccess) return hip_fail(e, "quotient join");
+    }
+    if (int rc = run_transform(p, kInverseToCoset, d_C, H, w, s)) return rc;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p->qjoin[i], 0);
+    if (e != hipSuccess) return hip_fail(e, "quotient join");
+    if (int rc = run_forward_pointwise(p, H, H, w, t1, t2, s)) return rc;
+    return run_transform(p, kCosetInverse, H, H, w, s);
+  }
   // Each of A, B, C: INTT with the coset shift g^k and 1/n fused in its last
   // pass, then a forward NTT: evaluations on g<w>.  The last pass of C's
   // forward NTT also applies the pointwise step (A B - C) / (g^n - 1), so H
