@@ -206,3 +206,43 @@ def test_schedules_are_byte_identical(cuda, opts, log2n):
     plan = _plan(field, log2n, **opts)
     for kind in KINDS:
         _check(to_host(_run(plan, kind, dx)), coracle.transform(field, kind, x), f"{opts} {kind} 2^{log2n}")
+
+
+@pytest.mark.parametrize("log2n", [10, 16, 22, 23])
+def test_quotient_workspace_size(cuda, log2n):
+    """Up to 2^22 the quotient runs A's and B's transforms on forked streams,
+    each with its own transform workspace: the quotient workspace is two
+    vectors plus three transform workspaces there, plus one above."""
+    from paper_2509_22684_amd import ntt_workspace_bytes, quotient_workspace_bytes
+
+    plan = _plan("bls12_381_fr", log2n)
+    n = 1 << log2n
+    ws = ntt_workspace_bytes(plan.handle)
+    assert quotient_workspace_bytes(plan.handle) == 2 * n * 32 + (3 if log2n <= 22 else 1) * ws
+
+
+def test_quotient_forked_chains_keep_stream_order(cuda):
+    """The forked chains start only after earlier work on the caller's stream
+    and finish before later work on it: two quotients on a side stream, with
+    A overwritten in between and H copied out after each, both equal the
+    oracle."""
+    import torch
+
+    field, log2n = "bn254_fr", 16
+    n = 1 << log2n
+    A1, A2, B, C = (si.uniform_field_vector(field, n, si.stream_seed(91, log2n, v)) for v in range(4))
+    plan = _plan(field, log2n)
+    dA, dB, dC = to_dev(A1, cuda), to_dev(B, cuda), to_dev(C, cuda)
+    a2 = to_dev(A2, cuda)
+    H = torch.empty_like(dA)
+    s = torch.cuda.Stream(cuda)
+    s.wait_stream(torch.cuda.current_stream(cuda))
+    with torch.cuda.stream(s):
+        plan.quotient(dA, dB, dC, H, stream=s)
+        H1 = H.clone()
+        dA.copy_(a2)
+        plan.quotient(dA, dB, dC, H, stream=s)
+        H2 = H.clone()
+    s.synchronize()
+    _check(to_host(H1), coracle.quotient(field, A1, B, C), "first quotient on a side stream")
+    _check(to_host(H2), coracle.quotient(field, A2, B, C), "second quotient after A changed")
