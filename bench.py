@@ -353,10 +353,11 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the host-resident pipeline leg")
-    ap.add_argument("--only", choices=["forward", "copy", "batch"], default=None,
+    ap.add_argument("--only", choices=["forward", "copy", "batch", "quotient"], default=None,
                     help="for profiler runs: only run --steps forward NTTs at 2^24, --steps plain device "
-                         "copies of one 512 MiB vector (the traffic calibration kernel), or --warmup + --steps "
-                         "graph replays of the 64-job batch, then exit")
+                         "copies of one 512 MiB vector (the traffic calibration kernel), --warmup + --steps "
+                         "graph replays of the 64-job batch, or --warmup + --steps quotient chains at 2^24 "
+                         "(the metric step), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -410,6 +411,24 @@ def main() -> int:
                           "workgroups": batch.grid, "status": batch.status(), "warmup": args.warmup,
                           "steps": args.steps}), flush=True)
         print(f"[bench] {args.warmup}+{args.steps} batch replays done", file=sys.stderr, flush=True)
+        return 0
+    if args.only == "quotient":
+        A, B, C = (to_dev(si.uniform_field_vector(FIELD, n, si.stream_seed(3, 0, v))) for v in range(3))
+        H = torch.empty_like(A)
+        plan = Plan(FIELD, LOG2N)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(args.warmup):
+            plan.quotient(A, B, C, H)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.quotient(A, B, C, H)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"quotient_ms_mean": e0.elapsed_time(e1) / max(1, args.steps), "warmup": args.warmup,
+                          "steps": args.steps}), flush=True)
+        print(f"[bench] {args.warmup}+{args.steps} quotient chains at 2^{LOG2N} done", file=sys.stderr, flush=True)
         return 0
     if args.only == "forward":
         # --warmup untimed forwards (clocks settle), then --steps forwards
