@@ -50,7 +50,10 @@ int hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? ZK_ENOMEM : ZK_EDEVICE;
 }
 
-enum Kind { kForward, kInverse, kCosetForward, kCosetInverse, kInverseToCoset };
+// kInverseRaw and kForwardShifted split the quotient's INTT-then-coset-NTT
+// differently: the inverse without its 1/n scaling, then the forward NTT
+// with g^k / n applied as it loads its input.
+enum Kind { kForward, kInverse, kCosetForward, kCosetInverse, kInverseToCoset, kInverseRaw, kForwardShifted };
 
 struct PassDesc {
   int log_r;
@@ -314,10 +317,14 @@ zk::PassArgs make_pass_args(const ntt_plan* p, Kind kind, size_t k, const void* 
   a.log_ns = d.log_ns;
   a.flags = 0;
   if (k == 0) {
-    if (kind == kInverse || kind == kCosetInverse || kind == kInverseToCoset) a.flags |= zk::kPassReverseIn;
+    if (kind == kInverse || kind == kCosetInverse || kind == kInverseToCoset || kind == kInverseRaw)
+      a.flags |= zk::kPassReverseIn;
     if (kind == kCosetForward) {
       a.flags |= zk::kPassPreTable;
       a.pre_table = p->coset_fwd;
+    } else if (kind == kForwardShifted) {
+      a.flags |= zk::kPassPreTable;
+      a.pre_table = p->inv_to_coset;
     }
   }
   if (k + 1 == P) {
@@ -366,7 +373,7 @@ int run_forward_pointwise(const ntt_plan* p, const void* in, void* out, void* wo
   const size_t P = p->passes.size();
   for (size_t k = 0; k < P; ++k) {
     const PassDesc& d = p->passes[k];
-    zk::PassArgs args = make_pass_args(p, kForward, k, in, out, work);
+    zk::PassArgs args = make_pass_args(p, kForwardShifted, k, in, out, work);
     if (k + 1 == P) {
       args.flags |= zk::kPassPostPointwise;
       args.pw_a = a;
@@ -526,27 +533,30 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
     Fe* dst[2] = {t1, t2};
     for (int i = 0; i < 2; ++i) {
       Fe* wi = ws ? w + (size_t)(i + 1) * ws : nullptr;
-      if (int rc = run_transform(p, kInverseToCoset, src[i], dst[i], wi, p->qside[i])) return rc;
-      if (int rc = run_transform(p, kForward, dst[i], dst[i], wi, p->qside[i])) return rc;
+      if (int rc = run_transform(p, kInverseRaw, src[i], dst[i], wi, p->qside[i])) return rc;
+      if (int rc = run_transform(p, kForwardShifted, dst[i], dst[i], wi, p->qside[i])) return rc;
       e = hipEventRecord(p->qjoin[i], p->qside[i]);
       if (e != hipSuccess) return hip_fail(e, "quotient join");
     }
-    if (int rc = run_transform(p, kInverseToCoset, d_C, H, w, s)) return rc;
+    if (int rc = run_transform(p, kInverseRaw, d_C, H, w, s)) return rc;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p->qjoin[i], 0);
     if (e != hipSuccess) return hip_fail(e, "quotient join");
     if (int rc = run_forward_pointwise(p, H, H, w, t1, t2, s)) return rc;
     return run_transform(p, kCosetInverse, H, H, w, s);
   }
-  // Each of A, B, C: INTT with the coset shift g^k and 1/n fused in its last
-  // pass, then a forward NTT: evaluations on g<w>.  The last pass of C's
-  // forward NTT also applies the pointwise step (A B - C) / (g^n - 1), so H
-  // holds the quotient's coset values without a separate pass over memory.
+  // Each of A, B, C: INTT without its 1/n, then a forward NTT that multiplies
+  // coefficient k by g^k / n as its first pass loads it: evaluations on
+  // g<w>.  (Scaling in the forward's first pass rather than the inverse's
+  // last pass puts the product where the pass has no inter-pass twiddle.)
+  // The last pass of C's forward NTT also applies the pointwise step
+  // (A B - C) / (g^n - 1), so H holds the quotient's coset values without a
+  // separate pass over memory.
   const void* src[3] = {d_A, d_B, d_C};
   Fe* dst[3] = {t1, t2, H};
   for (int v = 0; v < 3; ++v) {
-    if (int rc = run_transform(p, kInverseToCoset, src[v], dst[v], w, s)) return rc;
+    if (int rc = run_transform(p, kInverseRaw, src[v], dst[v], w, s)) return rc;
     if (v < 2) {
-      if (int rc = run_transform(p, kForward, dst[v], dst[v], w, s)) return rc;
+      if (int rc = run_transform(p, kForwardShifted, dst[v], dst[v], w, s)) return rc;
     } else if (int rc = run_forward_pointwise(p, H, H, w, t1, t2, s)) {
       return rc;
     }
@@ -555,8 +565,8 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
 }
 
 int quotient_coset_evals(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
-  if (int rc = transform_entry(p, kInverseToCoset, d_in, d_out, d_work, stream)) return rc;
-  return run_transform(p, kForward, d_out, d_out, d_work, static_cast<hipStream_t>(stream));
+  if (int rc = transform_entry(p, kInverseRaw, d_in, d_out, d_work, stream)) return rc;
+  return run_transform(p, kForwardShifted, d_out, d_out, d_work, static_cast<hipStream_t>(stream));
 }
 
 int quotient_pointwise(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_out,
