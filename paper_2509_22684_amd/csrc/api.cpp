@@ -531,16 +531,21 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
     if (e != hipSuccess) return hip_fail(e, "quotient fork");
     const void* src[2] = {d_A, d_B};
     Fe* dst[2] = {t1, t2};
-    for (int i = 0; i < 2; ++i) {
+    int rc = ZK_OK;
+    for (int i = 0; i < 2 && rc == ZK_OK; ++i) {
       Fe* wi = ws ? w + (size_t)(i + 1) * ws : nullptr;
-      if (int rc = run_transform(p, kInverseRaw, src[i], dst[i], wi, p->qside[i])) return rc;
-      if (int rc = run_transform(p, kForwardShifted, dst[i], dst[i], wi, p->qside[i])) return rc;
-      e = hipEventRecord(p->qjoin[i], p->qside[i]);
-      if (e != hipSuccess) return hip_fail(e, "quotient join");
+      rc = run_transform(p, kInverseRaw, src[i], dst[i], wi, p->qside[i]);
+      if (rc == ZK_OK) rc = run_transform(p, kForwardShifted, dst[i], dst[i], wi, p->qside[i]);
     }
-    if (int rc = run_transform(p, kInverseRaw, d_C, H, w, s)) return rc;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(s, p->qjoin[i], 0);
-    if (e != hipSuccess) return hip_fail(e, "quotient join");
+    if (rc == ZK_OK) rc = run_transform(p, kInverseRaw, d_C, H, w, s);
+    // join both side streams into s in every case, so that whatever was
+    // queued on them is ordered before later work on s, also after an error
+    for (int i = 0; i < 2; ++i) {
+      e = hipEventRecord(p->qjoin[i], p->qside[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, p->qjoin[i], 0);
+      if (e != hipSuccess && rc == ZK_OK) rc = hip_fail(e, "quotient join");
+    }
+    if (rc != ZK_OK) return rc;
     if (int rc = run_forward_pointwise(p, H, H, w, t1, t2, s)) return rc;
     return run_transform(p, kCosetInverse, H, H, w, s);
   }
@@ -722,30 +727,34 @@ int batch_enqueue(const ntt_batch* b, hipStream_t s) {
       if (e == hipSuccess) e = hipStreamWaitEvent(x, b->fork_ev, 0);
     if (e != hipSuccess) return hip_fail(e, "batch fork");
   }
+  int rc = ZK_OK;
   hipError_t e = zk::launch_batch(b->d_jobs, b->d_items, b->d_queues, b->nq_end, b->nitems, b->d_ctl, b->njobs,
                                   b->grid, s);
-  if (e != hipSuccess) return hip_fail(e, "batch launch");
-  for (const DirectWork& d : b->direct) {
+  if (e != hipSuccess) rc = hip_fail(e, "batch launch");
+  for (size_t k = 0; k < b->direct.size() && rc == ZK_OK; ++k) {
+    const DirectWork& d = b->direct[k];
     hipStream_t ds = b->sides.empty() ? s : b->sides[d.lane];
     if (d.pointwise) {
-      hipError_t e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in),
-                                                   static_cast<const Fe*>(d.in2), static_cast<const Fe*>(d.in3),
-                                                   static_cast<Fe*>(d.out), d.plan->zinv, d.plan->n, ds);
-      if (e != hipSuccess) return hip_fail(e, "pointwise launch");
+      e = zk::launch_quotient_pointwise(d.plan->field, static_cast<const Fe*>(d.in), static_cast<const Fe*>(d.in2),
+                                        static_cast<const Fe*>(d.in3), static_cast<Fe*>(d.out), d.plan->zinv,
+                                        d.plan->n, ds);
+      if (e != hipSuccess) rc = hip_fail(e, "pointwise launch");
       continue;
     }
-    for (size_t q = 0; q < d.pass.size(); ++q) {
+    for (size_t q = 0; q < d.pass.size() && rc == ZK_OK; ++q) {
       const PassDesc& pd = d.plan->passes[q];
-      hipError_t e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, 2, d.pass[q], ds);
-      if (e != hipSuccess) return hip_fail(e, "grouped pass launch");
+      e = zk::launch_pass(d.plan->field, pd.log_r, pd.log_tile, 2, d.pass[q], ds);
+      if (e != hipSuccess) rc = hip_fail(e, "grouped pass launch");
     }
   }
+  // join every side stream into s, also after an error, so that whatever was
+  // queued on them is ordered before later work on s
   for (size_t i = 0; i < b->sides.size(); ++i) {
     e = hipEventRecord(b->joins[i], b->sides[i]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, b->joins[i], 0);
-    if (e != hipSuccess) return hip_fail(e, "batch join");
+    if (e != hipSuccess && rc == ZK_OK) rc = hip_fail(e, "batch join");
   }
-  return ZK_OK;
+  return rc;
 }
 
 bool op_to_kind(int op, Kind* k) {
