@@ -246,3 +246,30 @@ def test_quotient_forked_chains_keep_stream_order(cuda):
     s.synchronize()
     _check(to_host(H1), coracle.quotient(field, A1, B, C), "first quotient on a side stream")
     _check(to_host(H2), coracle.quotient(field, A2, B, C), "second quotient after A changed")
+
+
+def test_quotient_one_plan_two_streams(cuda):
+    """One plan, two quotients enqueued back to back on two streams with
+    their own workspaces (the forked chains share the plan's side streams):
+    both equal the oracle."""
+    import torch
+
+    from paper_2509_22684_amd import quotient_poly, quotient_workspace_bytes
+
+    field, log2n = "bls12_381_fr", 14
+    n = 1 << log2n
+    plan = _plan(field, log2n)
+    host = [[si.uniform_field_vector(field, n, si.stream_seed(93, j, v)) for v in range(3)] for j in range(2)]
+    dev = [[to_dev(v, cuda) for v in h] for h in host]
+    Hs = [torch.empty_like(dev[0][0]) for _ in range(2)]
+    nb = quotient_workspace_bytes(plan.handle)
+    works = [torch.empty((nb + 31) // 32, 8, dtype=torch.int32, device=cuda) for _ in range(2)]
+    streams = [torch.cuda.Stream(cuda) for _ in range(2)]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream(cuda))
+    for j in range(2):
+        quotient_poly(plan.handle, *dev[j], Hs[j], works[j], streams[j])
+    for s in streams:
+        s.synchronize()
+    for j in range(2):
+        _check(to_host(Hs[j]), coracle.quotient(field, *host[j]), f"quotient on stream {j}")
