@@ -702,16 +702,65 @@ size_t batch_work_elems(const ntt_plan* const* plans, int njobs) {
   return total;
 }
 
+// Side streams and their events are recycled between batches (creating
+// them costs more host time than the rest of a small batch's set-up, and the
+// serving loop builds a batch per tick).  A batch holds its own while it
+// lives; free ones stay until the process ends.
+struct SidePool {
+  std::mutex mu;
+  std::vector<std::pair<int, hipStream_t>> streams;  // (device, stream)
+  std::vector<std::pair<int, hipEvent_t>> events;
+};
+SidePool& side_pool() {
+  static SidePool* pool = new SidePool();  // never destroyed: outlives every batch
+  return *pool;
+}
+
+hipError_t take_stream(int dev, hipStream_t* out) {
+  SidePool& sp = side_pool();
+  {
+    std::lock_guard<std::mutex> lock(sp.mu);
+    for (size_t i = 0; i < sp.streams.size(); ++i)
+      if (sp.streams[i].first == dev) {
+        *out = sp.streams[i].second;
+        sp.streams.erase(sp.streams.begin() + (long)i);
+        return hipSuccess;
+      }
+  }
+  return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+}
+
+hipError_t take_event(int dev, hipEvent_t* out) {
+  SidePool& sp = side_pool();
+  {
+    std::lock_guard<std::mutex> lock(sp.mu);
+    for (size_t i = 0; i < sp.events.size(); ++i)
+      if (sp.events[i].first == dev) {
+        *out = sp.events[i].second;
+        sp.events.erase(sp.events.begin() + (long)i);
+        return hipSuccess;
+      }
+  }
+  return hipEventCreateWithFlags(out, hipEventDisableTiming);
+}
+
+void give_back(int dev, const std::vector<hipStream_t>& streams, const std::vector<hipEvent_t>& events) {
+  SidePool& sp = side_pool();
+  std::lock_guard<std::mutex> lock(sp.mu);
+  for (hipStream_t x : streams)
+    if (x) sp.streams.emplace_back(dev, x);
+  for (hipEvent_t x : events)
+    if (x) sp.events.emplace_back(dev, x);
+}
+
 void free_batch(ntt_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-  for (hipStream_t x : b->sides)
-    if (x) (void)hipStreamDestroy(x);
-  for (hipEvent_t x : b->joins)
-    if (x) (void)hipEventDestroy(x);
-  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  std::vector<hipEvent_t> evs(b->joins);
+  evs.push_back(b->fork_ev);
+  give_back(b->device, b->sides, evs);
   if (b->d_mem) (void)hipFree(b->d_mem);
   delete b;
 }
@@ -1030,10 +1079,10 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     }
     b->sides.assign(nsides, nullptr);
     b->joins.assign(nsides, nullptr);
-    e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
+    e = take_event(dev, &b->fork_ev);
     for (size_t i = 0; i < nsides && e == hipSuccess; ++i) {
-      e = hipStreamCreateWithFlags(&b->sides[i], hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming);
+      e = take_stream(dev, &b->sides[i]);
+      if (e == hipSuccess) e = take_event(dev, &b->joins[i]);
     }
     if (e != hipSuccess) {
       free_batch(b);
