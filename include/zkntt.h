@@ -65,7 +65,11 @@ typedef enum {
   ZK_EDEVICE = -4       /* a HIP runtime call or kernel launch failed */
 } zk_status;
 
-/* Plan options.  Zero in any field selects the tuned default. */
+/* Plan options.  Zero in any schedule field selects the tuned schedule
+ * registered for (field, log2n) with ntt_tuning_register (the autotuner's
+ * measurements; the Python binding registers its database before it creates
+ * a plan), else the built-in default noted beside the field.  Every schedule
+ * computes the same bytes. */
 typedef struct {
   uint32_t twiddle_mode;    /* 0 default; 1 one precomputed table per pass in HBM;
                                2 two small tables and one extra multiplication per element */
@@ -79,13 +83,29 @@ typedef struct {
                                n = 2^18, so at most two passes there; 8 above), 4..9 */
 } ntt_plan_opts;
 
-#define ZK_FLAG_VALIDATE 1u /* check that inputs are canonical (adds a device-to-host sync) */
+#define ZK_FLAG_VALIDATE 1u /* check that inputs are canonical (adds a device-to-host sync, so calls on a
+                               stream that is being captured into a graph return ZK_EINVAL) */
 
 /* Create a plan for n = 2^log2n transforms over `field` on the current HIP
  * device: derives the root of unity and builds its twiddle and coset tables
  * in device memory.  opts may be NULL.  On success *out owns the plan. */
 int ntt_plan_create(ntt_plan **out, int field, uint32_t log2n, const ntt_plan_opts *opts);
 void ntt_plan_destroy(ntt_plan *p);
+
+/* Tuned schedules (Section V-A of the paper asks that such launch parameters
+ * be adapted to the GPU rather than picked by hand).  ntt_tuning_register
+ * records the schedule the autotuner measured fastest for (field, log2n) in
+ * a process-wide table; later ntt_plan_create calls fill each zero option
+ * field from it.  opts->flags must be 0.  Thread-safe; host only (no device
+ * call).  ntt_tuning_clear empties the table. */
+int ntt_tuning_register(int field, uint32_t log2n, const ntt_plan_opts *opts);
+void ntt_tuning_clear(void);
+/* The schedule ntt_plan_create would use for these arguments (zero fields
+ * resolved), without creating a plan: host only, no device needed.  opts may
+ * be NULL.  Same errors as ntt_plan_create's argument checks. */
+int ntt_plan_resolve_opts(int field, uint32_t log2n, const ntt_plan_opts *opts, ntt_plan_opts *resolved);
+/* The resolved schedule of an existing plan. */
+int ntt_plan_get_opts(const ntt_plan *p, ntt_plan_opts *out);
 
 /* Bytes of device workspace ntt_* calls on this plan need (0: none). */
 size_t ntt_workspace_bytes(const ntt_plan *p);
@@ -95,8 +115,9 @@ size_t ntt_plan_device_bytes(const ntt_plan *p);
 int ntt_plan_passes(const ntt_plan *p);
 
 /* Forward NTT: out_i = sum_j in_j w^(i j)  (Section II-B).
- * d_in may equal d_out.  d_work: ntt_workspace_bytes(p) bytes, or NULL when
- * that is 0; it must not overlap d_in or d_out. */
+ * d_in may equal d_out; otherwise they must not overlap.  d_work:
+ * ntt_workspace_bytes(p) bytes, or NULL when that is 0; it must not overlap
+ * d_in or d_out (ZK_EINVAL; the byte ranges are compared). */
 int ntt_forward(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
 
 /* Inverse NTT: out_j = n^-1 sum_i in_i w^(-i j).  Same buffer rules. */
@@ -122,7 +143,8 @@ size_t quotient_workspace_bytes(const ntt_plan *p);
  * (Z_H(x) = x^n - 1 takes the constant value g^n - 1 on the coset) and
  * returns in H the n coefficients of the polynomial with those coset values:
  *   H = cosetINTT( (cosetNTT(INTT A) . cosetNTT(INTT B) - cosetNTT(INTT C)) / (g^n - 1) ).
- * A, B, C are not modified; H must not overlap them or d_work.
+ * A, B, C are not modified; H must not overlap them or d_work, and d_work
+ * must not overlap A, B or C (ZK_EINVAL; the byte ranges are compared).
  * Up to n = 2^22 the transforms of A and B run on two streams of the plan,
  * forked from `stream` and joined back into it before C's forward NTT, so
  * the call still completes in the order of `stream`; calls on one plan from
@@ -138,12 +160,14 @@ int quotient_poly(const ntt_plan *p, const void *d_A, const void *d_B, const voi
  *   ntt_coset_inverse(H -> H).
  *
  * quotient_coset_evals: out = cosetNTT(INTT(in)), the values on g<w> of the
- * polynomial that takes the values `in` on <w> (the INTT's 1/n and the coset
- * shift g^j are fused into its last pass).  in may equal out; d_work as for
- * ntt_forward.
+ * polynomial that takes the values `in` on <w> (the INTT runs without its
+ * 1/n, and the forward NTT multiplies coefficient j by g^j / n as its first
+ * pass loads it).  in may equal out; d_work as for ntt_forward.
  * quotient_pointwise: out_i = (A_i B_i - C_i) / (g^n - 1) for i < n, each
  * element read before it is written, so out may equal any input. */
 int quotient_coset_evals(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
+int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_out,
+                       void *stream);
 
 /* Copy `bytes` (a multiple of 16; both pointers 16-byte aligned) from device
  * memory to pinned host memory (hipHostMalloc) with a kernel, asynchronously
@@ -154,8 +178,6 @@ int quotient_coset_evals(const ntt_plan *p, const void *d_in, void *d_out, void 
  * other.  ZK_EINVAL if host_dst is not pinned, mapped host memory or dev_src
  * is not device memory. */
 int zk_copy_to_host(void *host_dst, const void *dev_src, size_t bytes, void *stream);
-int quotient_pointwise(const ntt_plan *p, const void *d_A, const void *d_B, const void *d_C, void *d_out,
-                       void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent forward NTTs of uneven sizes and any field in

@@ -28,6 +28,11 @@ from ._lib import (  # noqa: F401
     ntt_inverse,
     ntt_plan_create,
     ntt_plan_destroy,
+    ntt_plan_get_opts,
+    ntt_plan_resolve_opts,
+    ntt_tuning_clear,
+    ntt_tuning_register,
+    register_tuning_db,
     ntt_plan_device_bytes,
     ntt_plan_passes,
     ntt_profile_passes,

@@ -55,6 +55,15 @@ def lib() -> ctypes.CDLL:
         L.ntt_plan_create.restype = ctypes.c_int
         L.ntt_plan_destroy.argtypes = [vp]
         L.ntt_plan_destroy.restype = None
+        L.ntt_tuning_register.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_Opts)]
+        L.ntt_tuning_register.restype = ctypes.c_int
+        L.ntt_tuning_clear.argtypes = []
+        L.ntt_tuning_clear.restype = None
+        L.ntt_plan_resolve_opts.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_Opts),
+                                            ctypes.POINTER(_Opts)]
+        L.ntt_plan_resolve_opts.restype = ctypes.c_int
+        L.ntt_plan_get_opts.argtypes = [vp, ctypes.POINTER(_Opts)]
+        L.ntt_plan_get_opts.restype = ctypes.c_int
         for name in ("ntt_workspace_bytes", "ntt_plan_device_bytes", "quotient_workspace_bytes"):
             getattr(L, name).argtypes = [vp]
             getattr(L, name).restype = sz
@@ -146,6 +155,80 @@ def ntt_plan_destroy(plan: int) -> None:
     lib().ntt_plan_destroy(plan)
 
 
+_OPT_KEYS = ("twiddle_mode", "log2_radix", "log2_tile", "flags", "log2_pass_radix")
+
+
+def _opts_dict(o: _Opts) -> dict:
+    return {k: int(getattr(o, k)) for k in _OPT_KEYS}
+
+
+def ntt_tuning_register(field, log2n: int, twiddle_mode: int = 0, log2_radix: int = 0, log2_tile: int = 0,
+                        log2_pass_radix: int = 0) -> None:
+    opts = _Opts(twiddle_mode, log2_radix, log2_tile, 0, log2_pass_radix)
+    _check(lib().ntt_tuning_register(_field_id(field), log2n, ctypes.byref(opts)), "ntt_tuning_register")
+
+
+def ntt_tuning_clear() -> None:
+    lib().ntt_tuning_clear()
+
+
+def ntt_plan_resolve_opts(field, log2n: int, twiddle_mode: int = 0, log2_radix: int = 0, log2_tile: int = 0,
+                          flags: int = 0, log2_pass_radix: int = 0) -> dict:
+    """The schedule ntt_plan_create would pick (host only; no device needed)."""
+    opts = _Opts(twiddle_mode, log2_radix, log2_tile, flags, log2_pass_radix)
+    out = _Opts()
+    _check(lib().ntt_plan_resolve_opts(_field_id(field), log2n, ctypes.byref(opts), ctypes.byref(out)),
+           "ntt_plan_resolve_opts")
+    return _opts_dict(out)
+
+
+def ntt_plan_get_opts(plan: int) -> dict:
+    out = _Opts()
+    _check(lib().ntt_plan_get_opts(plan, ctypes.byref(out)), "ntt_plan_get_opts")
+    return _opts_dict(out)
+
+
+_tuning_loaded = set()
+
+
+def register_tuning_db(device: str, path: str | None = None, force: bool = False) -> int:
+    """Register the stand-alone ("single") schedules that the autotuner's
+    database holds for `device` (a gcnArchName such as
+    "gfx950:sramecc+:xnack-"), so that plans created afterwards with zero
+    options run them.  Once per (device, path) unless force.  Returns the
+    number of schedules registered."""
+    import json
+
+    from .autotune import db_path
+
+    path = path or db_path()
+    key = (device, os.path.abspath(path))
+    if key in _tuning_loaded and not force:
+        return 0
+    _tuning_loaded.add(key)
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        entries = json.load(f).get("devices", {}).get(device, {})
+    count = 0
+    for k, e in entries.items():
+        field, log2n, mode = k.split(":")
+        if mode != "single" or field not in FIELDS:
+            continue
+        o = {kk: int(v) for kk, v in e["opts"].items() if kk in _OPT_KEYS and kk != "flags"}
+        ntt_tuning_register(field, int(log2n), **o)
+        count += 1
+    return count
+
+
+def _register_tuning_for_current_device() -> None:
+    import torch
+
+    dev = torch.cuda.current_device()
+    props = torch.cuda.get_device_properties(dev)
+    register_tuning_db(getattr(props, "gcnArchName", props.name))
+
+
 def ntt_workspace_bytes(plan: int) -> int:
     return lib().ntt_workspace_bytes(plan)
 
@@ -226,9 +309,11 @@ class Plan:
         self.field = field
         self.log2n = log2n
         self.n = 1 << log2n
-        self.opts = dict(twiddle_mode=twiddle_mode, log2_radix=log2_radix, log2_tile=log2_tile, flags=flags,
-                         log2_pass_radix=log2_pass_radix)
+        # zero options resolve through the tuning database's schedule for
+        # this device (registered once per process), then the defaults
+        _register_tuning_for_current_device()
         self.handle = ntt_plan_create(field, log2n, twiddle_mode, log2_radix, log2_tile, flags, log2_pass_radix)
+        self.opts = ntt_plan_get_opts(self.handle)
         self._work = None
         self._qwork = None
 

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -94,6 +95,7 @@ struct ntt_plan {
   hipEvent_t qfork = nullptr;
   hipEvent_t qjoin[2] = {nullptr, nullptr};
   std::mutex quotient_mu;  // one fork/join sequence at a time per plan
+  ntt_plan_opts opts{};    // the resolved schedule
 };
 
 namespace {
@@ -271,7 +273,82 @@ int build_plan(ntt_plan* p) {
   return ZK_OK;
 }
 
+// Tuned schedules registered by the caller (the autotuner's database):
+// ntt_plan_create fills every zero option from here before falling back to
+// the built-in defaults.
+struct TuningRegistry {
+  std::mutex mu;
+  std::map<std::pair<int, uint32_t>, ntt_plan_opts> opts;
+};
+TuningRegistry& tuning_registry() {
+  static TuningRegistry* r = new TuningRegistry();  // never destroyed: plans may be created at exit
+  return *r;
+}
+
+int field_adicity(int field) {
+  if (field == ZK_FIELD_BLS12_381_FR) return zk::Bls12_381Fr::TWO_ADICITY;
+  if (field == ZK_FIELD_BN254_FR) return zk::Bn254Fr::TWO_ADICITY;
+  if (field == ZK_FIELD_BLS12_377_FR) return zk::Bls12_377Fr::TWO_ADICITY;
+  return 0;
+}
+
+int check_opts(const ntt_plan_opts& o) {
+  if (o.twiddle_mode > 2) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0, 1 or 2");
+  if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 9))
+    return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..9");
+  if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
+  if (!(o.log2_tile == 0 || o.log2_tile == 10 || o.log2_tile == 11))
+    return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 10 or 11");
+  if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
+  return ZK_OK;
+}
+
+// The schedule a plan for (field, log2n) runs: every zero field of `in`
+// from the registered tuned schedule, then from the built-in defaults.
+int resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* in, ntt_plan_opts* out) {
+  const int adicity = field_adicity(field);
+  if (!adicity) return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
+  if (log2n > (uint32_t)adicity)
+    return fail(ZK_EUNSUPPORTED, "log2n " + std::to_string(log2n) + " exceeds the field's 2-adicity " +
+                                     std::to_string(adicity));
+  ntt_plan_opts o{};
+  if (in) o = *in;
+  if (int rc = check_opts(o)) return rc;
+  {
+    TuningRegistry& reg = tuning_registry();
+    std::lock_guard<std::mutex> lock(reg.mu);
+    auto it = reg.opts.find({field, log2n});
+    if (it != reg.opts.end()) {
+      const ntt_plan_opts& t = it->second;
+      if (!o.twiddle_mode) o.twiddle_mode = t.twiddle_mode;
+      if (!o.log2_radix) o.log2_radix = t.log2_radix;
+      if (!o.log2_tile) o.log2_tile = t.log2_tile;
+      if (!o.log2_pass_radix) o.log2_pass_radix = t.log2_pass_radix;
+    }
+  }
+  // Built-in defaults.  Register radix: radix-2 rounds (two elements per
+  // thread, twice the threads per tile) up to 2^18, where a transform has
+  // too few tiles to fill the chip and more waves per tile shorten each
+  // pass; radix-4 above, where every CU is busy and fewer instructions per
+  // element win.  Pass depth: up to 2^18 two passes of at most 2^9 points (a
+  // third pass would cost another launch or, in a batch, another round of
+  // tiles and dependency waits); above, passes of at most 2^8 points, which
+  // measured fastest at 2^24.
+  if (!o.twiddle_mode) o.twiddle_mode = 1;
+  if (!o.log2_radix) o.log2_radix = log2n <= 18 ? 1 : 2;
+  if (!o.log2_tile) o.log2_tile = 10;
+  if (!o.log2_pass_radix) o.log2_pass_radix = log2n <= 18 ? 9 : 8;
+  *out = o;
+  return ZK_OK;
+}
+
 bool aligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
+
+// [a, a + na) and [b, b + nb) share a byte.
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return na && nb && x < y + nb && y < x + na;
+}
 
 int check_device(const ntt_plan* p) {
   int dev = -1;
@@ -282,6 +359,13 @@ int check_device(const ntt_plan* p) {
 }
 
 int validate_input(ntt_plan* p, const void* x, hipStream_t s) {
+  // The check reads its count back to the host and waits for the stream,
+  // which a stream being captured into a graph cannot do.
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t ce = hipStreamIsCapturing(s, &cs);
+  if (ce != hipSuccess) return hip_fail(ce, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(ZK_EINVAL, "ZK_FLAG_VALIDATE needs a host synchronisation and cannot run under stream capture");
   std::lock_guard<std::mutex> lock(p->validate_mu);
   hipError_t e = hipMemsetAsync(p->d_count, 0, sizeof(uint32_t), s);
   if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(counter)");
@@ -393,8 +477,12 @@ int transform_entry(const ntt_plan* p, Kind kind, const void* in, void* out, voi
   if (workspace_elems(p)) {
     if (!work) return fail(ZK_EINVAL, "this plan needs a workspace (ntt_workspace_bytes)");
     if (!aligned(work)) return fail(ZK_EINVAL, "workspace must be 256-byte aligned");
-    if (work == in || work == out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
+    const size_t vb = p->n * sizeof(Fe), wb = workspace_elems(p) * sizeof(Fe);
+    if (overlaps(work, wb, in, vb) || overlaps(work, wb, out, vb))
+      return fail(ZK_EINVAL, "workspace must not overlap the vectors");
   }
+  if (in != out && overlaps(in, p->n * sizeof(Fe), out, p->n * sizeof(Fe)))
+    return fail(ZK_EINVAL, "in and out must be the same buffer or not overlap");
   if (int rc = check_device(p)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->flags & ZK_FLAG_VALIDATE) {
@@ -410,42 +498,20 @@ extern "C" {
 int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_opts* opts) {
   if (!out) return fail(ZK_EINVAL, "null output pointer");
   *out = nullptr;
-  int adicity = 0;
-  if (field == ZK_FIELD_BLS12_381_FR) adicity = zk::Bls12_381Fr::TWO_ADICITY;
-  else if (field == ZK_FIELD_BN254_FR) adicity = zk::Bn254Fr::TWO_ADICITY;
-  else if (field == ZK_FIELD_BLS12_377_FR) adicity = zk::Bls12_377Fr::TWO_ADICITY;
-  else return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
-  if (log2n > (uint32_t)adicity)
-    return fail(ZK_EUNSUPPORTED, "log2n " + std::to_string(log2n) + " exceeds the field's 2-adicity " +
-                                     std::to_string(adicity));
   ntt_plan_opts o{};
-  if (opts) o = *opts;
-  if (o.twiddle_mode > 2) return fail(ZK_EUNSUPPORTED, "twiddle_mode must be 0, 1 or 2");
-  if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 9))
-    return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..9");
-  if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
-  if (!(o.log2_tile == 0 || o.log2_tile == 10 || o.log2_tile == 11))
-    return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 10 or 11");
-  if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
+  if (int rc = resolve_opts(field, log2n, opts, &o)) return rc;
 
   ntt_plan* p = new (std::nothrow) ntt_plan();
   if (!p) return fail(ZK_ENOMEM, "host allocation failed");
   p->field = field;
   p->log_n = log2n;
   p->n = 1ull << log2n;
-  // Default register radix: radix-2 rounds (two elements per thread, twice
-  // the threads per tile) up to 2^18, where a transform has too few tiles to
-  // fill the chip and more waves per tile shorten each pass; radix-4 above,
-  // where every CU is busy and fewer instructions per element win.
-  p->log_e = o.log2_radix ? (int)o.log2_radix : (log2n <= 18 ? 1 : 2);
+  p->log_e = (int)o.log2_radix;
   p->flags = o.flags;
-  p->twiddle_mode = o.twiddle_mode ? o.twiddle_mode : 1;
-  // Default pass depth: up to 2^18 two passes of at most 2^9 points (a third
-  // pass would cost another launch or, in a batch, another round of tiles
-  // and dependency waits); above, passes of at most 2^8 points, which
-  // measured fastest at 2^24.
-  p->max_log_r = o.log2_pass_radix ? o.log2_pass_radix : (log2n <= 18 ? 9 : 8);
-  p->log_tile = o.log2_tile ? o.log2_tile : 10;
+  p->twiddle_mode = o.twiddle_mode;
+  p->max_log_r = o.log2_pass_radix;
+  p->log_tile = o.log2_tile;
+  p->opts = o;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -474,6 +540,36 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
 }
 
 void ntt_plan_destroy(ntt_plan* p) { free_plan(p); }
+
+int ntt_tuning_register(int field, uint32_t log2n, const ntt_plan_opts* opts) {
+  if (!opts) return fail(ZK_EINVAL, "null options");
+  const int adicity = field_adicity(field);
+  if (!adicity) return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
+  if (log2n > (uint32_t)adicity) return fail(ZK_EUNSUPPORTED, "log2n exceeds the field's 2-adicity");
+  if (int rc = check_opts(*opts)) return rc;
+  if (opts->flags) return fail(ZK_EINVAL, "a tuned schedule carries no flags");
+  TuningRegistry& reg = tuning_registry();
+  std::lock_guard<std::mutex> lock(reg.mu);
+  reg.opts[{field, log2n}] = *opts;
+  return ZK_OK;
+}
+
+void ntt_tuning_clear(void) {
+  TuningRegistry& reg = tuning_registry();
+  std::lock_guard<std::mutex> lock(reg.mu);
+  reg.opts.clear();
+}
+
+int ntt_plan_resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* opts, ntt_plan_opts* resolved) {
+  if (!resolved) return fail(ZK_EINVAL, "null output pointer");
+  return resolve_opts(field, log2n, opts, resolved);
+}
+
+int ntt_plan_get_opts(const ntt_plan* p, ntt_plan_opts* out) {
+  if (!p || !out) return fail(ZK_EINVAL, "null argument");
+  *out = p->opts;
+  return ZK_OK;
+}
 
 size_t ntt_workspace_bytes(const ntt_plan* p) { return p ? workspace_elems(p) * sizeof(Fe) : 0; }
 
@@ -507,8 +603,14 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
   if (!d_A || !d_B || !d_C || !d_H || !d_work) return fail(ZK_EINVAL, "null pointer");
   if (!aligned(d_A) || !aligned(d_B) || !aligned(d_C) || !aligned(d_H) || !aligned(d_work))
     return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
-  if (d_H == d_A || d_H == d_B || d_H == d_C || d_work == d_H)
-    return fail(ZK_EINVAL, "H must not alias A, B, C or the workspace");
+  {
+    const size_t vb = p->n * sizeof(Fe), wb = quotient_workspace_bytes(p);
+    for (const void* x : {d_A, d_B, d_C, static_cast<const void*>(d_work)})
+      if (overlaps(d_H, vb, x, x == d_work ? wb : vb))
+        return fail(ZK_EINVAL, "H must not overlap A, B, C or the workspace");
+    for (const void* x : {d_A, d_B, d_C})
+      if (overlaps(d_work, wb, x, vb)) return fail(ZK_EINVAL, "the workspace must not overlap A, B or C");
+  }
   if (int rc = check_device(p)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->flags & ZK_FLAG_VALIDATE) {
@@ -867,7 +969,9 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
                                          std::to_string(zk::kBatchTileLog) + " points");
     if (workspace_elems(p)) {
       if (!sp.work || !aligned(sp.work)) return fail(ZK_EINVAL, "batch job needs an aligned workspace");
-      if (sp.work == sp.in || sp.work == sp.out) return fail(ZK_EINVAL, "workspace must not alias the vectors");
+      const size_t vb = p->n * sizeof(Fe), wb = workspace_elems(p) * sizeof(Fe);
+      if (overlaps(sp.work, wb, sp.in, vb) || overlaps(sp.work, wb, sp.out, vb))
+        return fail(ZK_EINVAL, "workspace must not overlap the vectors");
     }
     J.kind = zk::kJobTransform;
     J.npasses = (uint32_t)p->passes.size();

@@ -7,7 +7,7 @@
 // the NTT butterflies: FF_add, FF_sub and FF_mul, with FF_mul and FF_sqr
 // taking almost all of the NTT's time.  It attributes most of the add/sub
 // latency to the branches that decide the conditional reduction (Section
-// IV-B1 and the micro-architecture analysis of Section IV-C); here every
+// IV-B and the micro-architecture analysis of Section IV-C); here every
 // reduction is a branchless borrow-select, so the lanes of a wavefront never
 // diverge.
 //

@@ -312,6 +312,36 @@ def test_c_oracle_equals_python_oracle(field, log2n):
 
 
 @pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr", "bls12_377_fr"])
+@pytest.mark.parametrize("log2n", [13, 14])
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_c_oracle_threaded_stages_equal_python_oracle(field, log2n, threads):
+    """From n = 2^13 the C oracle splits every butterfly stage over threads
+    (a stage has n/2 >= 4096 butterflies); with 1, 3 (uneven ranges) and 8
+    threads each kind equals the Python-integer oracle element by element."""
+    F = ref.FIELDS[field]
+    n = 1 << log2n
+    x = si.uniform_field_vector(field, n, 700 + log2n)
+    ys = si.limbs_to_ints(x)
+    for kind in ("forward", "inverse", "coset_forward", "coset_inverse"):
+        got = coracle.transform(field, kind, x, threads=threads)
+        assert si.limbs_to_ints(got) == ref.transform_mont(F, kind, ys), kind
+
+
+@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr", "bls12_377_fr"])
+@pytest.mark.parametrize("log2n", [11, 12, 13])
+@pytest.mark.parametrize("threads", [3, 8])
+def test_c_oracle_threaded_quotient_equals_python_oracle(field, log2n, threads):
+    """The quotient chain with threaded conversions, scalings, stages and
+    pointwise step (threaded from n = 2^12 for the elementwise work and from
+    2^13 for the stages) equals the Python oracle."""
+    F = ref.FIELDS[field]
+    n = 1 << log2n
+    A, B, C = (si.uniform_field_vector(field, n, 800 + log2n + v) for v in range(3))
+    want = ref.quotient_mont(F, *(si.limbs_to_ints(v) for v in (A, B, C)))
+    assert si.limbs_to_ints(coracle.quotient(field, A, B, C, threads=threads)) == want
+
+
+@pytest.mark.parametrize("field", ["bls12_381_fr", "bn254_fr", "bls12_377_fr"])
 def test_c_oracle_large_n_horner(field):
     """At n = 2^16 the C oracle's outputs equal a(w^i) evaluated by Horner in
     Python integers, and its own Horner routine agrees."""
@@ -327,6 +357,15 @@ def test_c_oracle_large_n_horner(field):
         assert F.from_mont([out[i]])[0] == ref.horner(F, coeffs, pow(w, i, F.p))
     spot = si.limbs_to_ints(coracle.eval_at_roots(field, x, np.array(idx, dtype=np.uint64)))
     assert spot == [out[i] for i in idx]
+    # coset forward: a(g w^i) by Horner; inverse and coset inverse undo
+    # their forward transforms (threaded at this size)
+    cos = si.limbs_to_ints(coracle.transform(field, "coset_forward", x, threads=6))
+    for i in idx:
+        assert F.from_mont([cos[i]])[0] == ref.horner(F, coeffs, F.generator * pow(w, i, F.p) % F.p)
+    fwd = coracle.transform(field, "forward", x, threads=5)
+    assert np.array_equal(coracle.transform(field, "inverse", fwd, threads=7), x)
+    cf = coracle.transform(field, "coset_forward", x, threads=4)
+    assert np.array_equal(coracle.transform(field, "coset_inverse", cf, threads=3), x)
 
 
 def test_c_oracle_rejects_bad_sizes():
