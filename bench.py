@@ -72,16 +72,54 @@ def valu_from_profile(khash: str):
     return d.get("valu_wave_instructions_per_launch")
 
 
-def cpu_baseline(x_host) -> dict:
-    """The C oracle on the host cores: one forward NTT at n = 2^24."""
+def cpu_baseline(x_host, runs: int = 3) -> dict:
+    """The C oracle on the host cores: one forward NTT at n = 2^24, median of
+    `runs` runs."""
     from oracle import coracle
 
     threads = coracle.default_threads()
-    t0 = time.perf_counter()
-    coracle.transform(FIELD, "forward", x_host, threads=threads)
-    dt = time.perf_counter() - t0
+    dts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        coracle.transform(FIELD, "forward", x_host, threads=threads)
+        dts.append(time.perf_counter() - t0)
+    dt = statistics.median(dts)
     return {"value": (1 << LOG2N) / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
-            "sample": f"one forward NTT at n=2^24 (BLS12-381 Fr) with the C oracle, {dt:.2f} s wall"}
+            "sample": f"one forward NTT at n=2^24 (BLS12-381 Fr) with the C oracle, median of {runs} runs: "
+                      + ", ".join(f"{d:.2f}" for d in dts) + " s wall"}
+
+
+def peaks_leg(dev) -> dict:
+    """Measured roofline denominators (zk_microbench): the all-CU rates of
+    the instructions the pass kernel is made of, Montgomery products, and a
+    streaming copy's HBM bandwidth."""
+    import torch
+
+    from paper_2509_22684_amd import zk_microbench
+
+    small = torch.empty(1 << 20, 8, dtype=torch.int32, device=dev)  # 32 MiB: per-thread results
+    out = {}
+    for kind, iters in (("mad_u64_u32", 2048), ("fma_f64", 2048), ("add_u32", 2048), ("addc_u32", 1024),
+                        ("mad_addc", 1024), ("ffmul_bls12_381", 128), ("ffmul_k2", 192), ("ffmul_k4", 96)):
+        rate, ms = zk_microbench(kind, small, iters=iters, reps=5)
+        out[kind] = {"per_s": rate, "ms_per_launch": ms, "iters": iters}
+    big = torch.empty(1 << 26, 8, dtype=torch.int32, device=dev)  # 2 GiB: 1 GiB read, 1 GiB written
+    rate, ms = zk_microbench("copy", big, reps=5)
+    out["copy"] = {"bytes_per_s": rate, "ms_per_launch": ms, "bytes_per_launch": big.numel() * 4}
+    del big
+    spec = PEAK_MAD_PER_S
+    out["summary"] = {
+        "mad_u64_u32_T_per_s": out["mad_u64_u32"]["per_s"] / 1e12,
+        "mad_u64_u32_over_spec_issue_rate": out["mad_u64_u32"]["per_s"] / spec,
+        "fma_f64_T_per_s": out["fma_f64"]["per_s"] / 1e12,
+        "add_u32_T_per_s": out["add_u32"]["per_s"] / 1e12,
+        "addc_u32_T_per_s": out["addc_u32"]["per_s"] / 1e12,
+        "fips_column_steps_T_per_s": out["mad_addc"]["per_s"] / 1e12,
+        "ffmul_G_per_s": {k: out[f"ffmul_{k}"]["per_s"] / 1e9 for k in ("bls12_381", "k2", "k4")},
+        "hbm_copy_TB_per_s": out["copy"]["bytes_per_s"] / 1e12,
+        "spec_issue_rate_T_per_s": spec / 1e12,
+    }
+    return out
 
 
 def cpu_one_core(log2n: int = 20) -> dict:
@@ -218,15 +256,17 @@ def batch_leg(dev, reps: int = 20) -> dict:
     }
 
 
-def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0)) -> dict:
+def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0, 1.25, 1.5)) -> dict:
     """Quotient jobs on BLS12-381 Fr (log2 n uniform in [14, 22], seed 5)
     served with continuous batching.  mu = solo throughput on the same size
     mix (one quotient_poly call at a time); then Poisson arrivals at
-    lambda = rho mu for each rho under a 200 GB HBM budget, and once more at
+    lambda = rho mu for each rho under a 200 GB HBM budget (rho above 1
+    offers more than one-at-a-time execution can sustain), and once more at
     rho = 1 under a 2 GB budget so that admission has to hold jobs back.
     Each job's A, B, C come from a device-resident pool of one seeded vector
     triple per size, copied into the job's own buffers on admission; latency
-    runs from arrival to H ready on the device."""
+    runs from arrival to H ready on the device; slowdown is a job's latency
+    over the time of its size alone."""
     import numpy as np
     import torch
 
@@ -242,11 +282,20 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0)) -> dict:
     for L in pool:  # plans (twiddle tables) stay resident across jobs
         ex.plan(L)
 
-    # mu: the size mix run solo, one job after another
+    # mu: the size mix run solo, one job after another; and each size alone
     H = {L: torch.empty_like(pool[L][0]) for L in pool}
     for L in pool:
         ex.plan(L).quotient(*pool[L], H[L])
     torch.cuda.synchronize()
+    solo_s = {}
+    for L in pool:
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            ex.plan(L).quotient(*pool[L], H[L])
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        solo_s[L] = statistics.median(ts)
     t0 = time.perf_counter()
     for L in sizes:
         ex.plan(L).quotient(*pool[L], H[L])
@@ -260,18 +309,23 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0)) -> dict:
         ex.ticks = ex.tick_jobs = 0
         srv = QuotientServer(ex, budget_bytes=budget)
         res = srv.run(reqs, realtime=True)
-        out = summarize(res)
+        out = summarize(res, solo_s)
         out.update({"rate_per_s": rate, "budget_bytes": budget, "ticks": ex.ticks,
                     "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "max_inflight": srv.max_inflight,
                     "peak_bytes": srv.peak_bytes})
         return out
 
     run(mu, 200 << 30)  # warm-up
-    runs = [dict(rho=r, **run(r * mu, 200 << 30)) for r in rhos]
+    runs = []
+    for r in rhos:
+        print(f"[bench] serving rho={r}", file=sys.stderr, flush=True)
+        runs.append(dict(rho=r, **run(r * mu, 200 << 30)))
     admission = dict(rho=1.0, **run(mu, 2 << 30))
     return {"workload": f"{njobs} quotient jobs, log2 n uniform in [14,22] (seed 5), BLS12-381 Fr, Poisson arrivals "
                         "at rho x solo throughput",
-            "mu_solo_jobs_per_s": mu, "runs": runs, "admission_2GB": admission}
+            "lanes": {"bounds_log2n": list(ex.lane_bounds), "ticks_enqueued_ahead": 2},
+            "mu_solo_jobs_per_s": mu, "solo_ms_by_log2n": {str(L): t * 1e3 for L, t in solo_s.items()},
+            "runs": runs, "admission_2GB": admission}
 
 
 def host_pipeline_leg(dev, log2n: int = 22, njobs: int = 8) -> dict:
@@ -353,11 +407,12 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the host-resident pipeline leg")
-    ap.add_argument("--only", choices=["forward", "copy", "batch", "quotient"], default=None,
+    ap.add_argument("--only", choices=["forward", "copy", "batch", "quotient", "peaks", "serve"], default=None,
                     help="for profiler runs: only run --steps forward NTTs at 2^24, --steps plain device "
                          "copies of one 512 MiB vector (the traffic calibration kernel), --warmup + --steps "
                          "graph replays of the 64-job batch, or --warmup + --steps quotient chains at 2^24 "
-                         "(the metric step), then exit")
+                         "(the metric step), or the micro-benchmarks of the roofline denominators "
+                         "(peaks), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -376,6 +431,15 @@ def main() -> int:
     def to_dev(a):
         return torch.from_numpy(np.ascontiguousarray(a).view(np.int32).copy()).to(dev)
 
+    if args.only == "serve":
+        print(json.dumps(serve_leg(dev)), flush=True)
+        print("[bench] serving leg done", file=sys.stderr, flush=True)
+        return 0
+    if args.only == "peaks":
+        res = peaks_leg(dev)
+        print(json.dumps(res), flush=True)
+        print("[bench] micro-benchmarks done", file=sys.stderr, flush=True)
+        return 0
     if args.only == "copy":
         src = torch.randint(-(1 << 31), (1 << 31) - 1, (n, 8), dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -499,6 +563,9 @@ def main() -> int:
     khash = kernel_hash()
     traffic = traffic_from_profile(khash)
     valu = valu_from_profile(khash)
+    print("[bench] micro-benchmarks (measured peaks)", file=sys.stderr, flush=True)
+    peaks = peaks_leg(dev)
+    mad_measured = peaks["mad_u64_u32"]["per_s"]
     roofline = {
         "bound": "alu",
         "kernel": f"ntt_pass_kernel<Bls12_381Fr, LOG_R={log_r}, LOG_TILE={plan.opts['log2_tile'] or 10}, "
@@ -507,6 +574,9 @@ def main() -> int:
         "peak": PEAK_MAD_PER_S / 1e12,
         "unit": "T MAD/s",
         "frac": achieved / PEAK_MAD_PER_S,
+        "peak_derivation": "256 CU x 4 SIMD x 16 lanes x 2.4 GHz: one v_mad_u64_u32 per lane per cycle",
+        "measured_peak": mad_measured / 1e12,
+        "frac_of_measured_peak": achieved / mad_measured,
         "traffic": traffic,
         "avg_launch_ms": avg_pass_ms,
         "pass_ms": pass_ms,
@@ -538,6 +608,7 @@ def main() -> int:
                    "field": FIELD, "log2n": LOG2N, "transforms_per_step": 7},
         "forward_ntt_2e24": {"ms_median": fwd_med, "elements_per_s": n / (fwd_med * 1e-3), "passes": npass},
         "roofline": roofline,
+        "measured_peaks": peaks["summary"],
     }
     if not args.no_batch:
         print("[bench] batched vs per-launch (64 jobs)", file=sys.stderr, flush=True)

@@ -106,6 +106,12 @@ void ntt_tuning_clear(void);
 int ntt_plan_resolve_opts(int field, uint32_t log2n, const ntt_plan_opts *opts, ntt_plan_opts *resolved);
 /* The resolved schedule of an existing plan. */
 int ntt_plan_get_opts(const ntt_plan *p, ntt_plan_opts *out);
+/* Bytes of device tables ntt_plan_create would allocate for these
+ * arguments (what ntt_plan_device_bytes reports for the plan), computed on
+ * the host without creating the plan or touching the device; 0 if the
+ * arguments are unsupported (zk_last_error says why).  For admission
+ * control: a caller can budget a plan before it exists. */
+size_t ntt_plan_table_bytes(int field, uint32_t log2n, const ntt_plan_opts *opts);
 
 /* Bytes of device workspace ntt_* calls on this plan need (0: none). */
 size_t ntt_workspace_bytes(const ntt_plan *p);
@@ -119,6 +125,18 @@ int ntt_plan_passes(const ntt_plan *p);
  * ntt_workspace_bytes(p) bytes, or NULL when that is 0; it must not overlap
  * d_in or d_out (ZK_EINVAL; the byte ranges are compared). */
 int ntt_forward(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
+
+/* ntt_forward without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The library keeps
+ * a fixed workspace of 2^20 elements (32 MiB) per device for it, held until
+ * the process ends; plans whose ntt_workspace_bytes exceeds that (n > 2^20)
+ * return ZK_EUNSUPPORTED.  Same result and buffer rules as ntt_forward.
+ * Every call on one device shares that workspace and leaves its contents
+ * behind: calls that may overlap in time on one device (different streams,
+ * or threads enqueuing without ordering) race and must be serialised by the
+ * caller. */
+int ntt_forward_noalloc(const ntt_plan *p, const void *d_in, void *d_out, void *stream);
 
 /* Inverse NTT: out_j = n^-1 sum_i in_i w^(-i j).  Same buffer rules. */
 int ntt_inverse(const ntt_plan *p, const void *d_in, void *d_out, void *d_work, void *stream);
@@ -276,6 +294,10 @@ int ntt_batch_set_spin_limit(ntt_batch *b, uint32_t polls);
 int ntt_batch_items(const ntt_batch *b);
 int ntt_batch_grid(const ntt_batch *b);
 
+/* Frees the batch.  Its device descriptors go back to a per-process pool
+ * of the library (hipFree would wait for the whole device); a later batch
+ * reuses them only after the last launch of this one has completed, so a
+ * batch may be destroyed while its launch is still running. */
 void ntt_batch_destroy(ntt_batch *b);
 
 /* One-shot: build, launch without a graph, synchronise `stream`, check the
@@ -289,6 +311,39 @@ int ntt_batch_forward(const ntt_plan *const *plans, void *const *d_bufs, int njo
  * the number of passes (> 0) or a zk_status.  Synchronises the stream. */
 int ntt_profile_passes(const ntt_plan *p, int kind, const void *d_in, void *d_out, void *d_work, void *stream,
                        float *ms_per_pass, int max_passes);
+
+/* Measurement helper: the all-CU rate of the units the NTT's rooflines are
+ * drawn on (the paper places its NTT kernels on the GPU's INT32 roofline,
+ * Section IV-C).  One warm-up launch, then `reps` launches timed with HIP
+ * events on `stream`; synchronises the stream.
+ *   ZK_MB_MAD_U64_U32      v_mad_u64_u32 instructions/s (8 independent chains per lane)
+ *   ZK_MB_FMA_F64          v_fma_f64 instructions/s
+ *   ZK_MB_ADD_U32          v_add_u32 instructions/s
+ *   ZK_MB_ADDC_U32         v_add_co_u32 + v_addc_co_u32 instructions/s (carry chains)
+ *   ZK_MB_MAD_ADDC         FIPS column steps/s (v_mad_u64_u32 plus the v_addc_co_u32 of its carry)
+ *   ZK_MB_FFMUL_BLS12_381  Montgomery products/s over BLS12-381 Fr (three interleaved per thread,
+ *                          four waves per SIMD, like the pass kernels); ZK_MB_FFMUL_K2 and
+ *                          ZK_MB_FFMUL_K4 interleave two and four
+ *   ZK_MB_COPY             bytes/s read plus written by a streaming copy of the
+ *                          first half of d_buf into its second half
+ * `iters`: loop trips per thread (ALU kinds; ignored by the copy).  d_buf:
+ * 256-byte aligned device memory of buf_bytes; the ALU kinds store one
+ * 8-byte value per launched thread (256 CUs x 2048 threads: 4 MiB) and
+ * return ZK_EINVAL if it is smaller.  Writes the rate to *ops_per_s and the
+ * mean launch time to *ms_per_launch. */
+typedef enum {
+  ZK_MB_MAD_U64_U32 = 0,
+  ZK_MB_FMA_F64 = 1,
+  ZK_MB_ADD_U32 = 2,
+  ZK_MB_ADDC_U32 = 3,
+  ZK_MB_MAD_ADDC = 4,
+  ZK_MB_FFMUL_BLS12_381 = 5,
+  ZK_MB_COPY = 6,
+  ZK_MB_FFMUL_K2 = 7,
+  ZK_MB_FFMUL_K4 = 8
+} zk_microbench_kind;
+int zk_microbench(int kind, uint32_t iters, void *d_buf, size_t buf_bytes, void *stream, int reps,
+                  double *ops_per_s, float *ms_per_launch);
 
 /* Thread-local description of the calling thread's last failure. */
 const char *zk_last_error(void);

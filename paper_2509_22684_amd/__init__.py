@@ -30,6 +30,7 @@ from ._lib import (  # noqa: F401
     ntt_plan_destroy,
     ntt_plan_get_opts,
     ntt_plan_resolve_opts,
+    ntt_plan_table_bytes,
     ntt_tuning_clear,
     ntt_tuning_register,
     register_tuning_db,
@@ -42,5 +43,7 @@ from ._lib import (  # noqa: F401
     quotient_pointwise,
     quotient_workspace_bytes,
     zk_copy_to_host,
+    zk_microbench,
+    ntt_forward_noalloc,
     zk_last_error,
 )

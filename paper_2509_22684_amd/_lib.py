@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libzkntt.so")
 
 FIELDS = {"bls12_381_fr": 1, "bn254_fr": 2, "bls12_377_fr": 3}
-FIELD_ADICITY = {"bls12_381_fr": 32, "bn254_fr": 28}
+FIELD_ADICITY = {"bls12_381_fr": 32, "bn254_fr": 28, "bls12_377_fr": 47}
 
 ZK_FLAG_VALIDATE = 1
 
@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
         L.ntt_plan_resolve_opts.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_Opts),
                                             ctypes.POINTER(_Opts)]
         L.ntt_plan_resolve_opts.restype = ctypes.c_int
+        L.ntt_plan_table_bytes.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_Opts)]
+        L.ntt_plan_table_bytes.restype = sz
         L.ntt_plan_get_opts.argtypes = [vp, ctypes.POINTER(_Opts)]
         L.ntt_plan_get_opts.restype = ctypes.c_int
         for name in ("ntt_workspace_bytes", "ntt_plan_device_bytes", "quotient_workspace_bytes"):
@@ -72,6 +74,8 @@ def lib() -> ctypes.CDLL:
         for name in ("ntt_forward", "ntt_inverse", "ntt_coset_forward", "ntt_coset_inverse"):
             getattr(L, name).argtypes = [vp, vp, vp, vp, vp]
             getattr(L, name).restype = ctypes.c_int
+        L.ntt_forward_noalloc.argtypes = [vp, vp, vp, vp]
+        L.ntt_forward_noalloc.restype = ctypes.c_int
         L.quotient_poly.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.quotient_poly.restype = ctypes.c_int
         L.quotient_coset_evals.argtypes = [vp, vp, vp, vp, vp]
@@ -102,6 +106,9 @@ def lib() -> ctypes.CDLL:
         L.ntt_batch_create_jobs.restype = ctypes.c_int
         L.ntt_batch_forward.argtypes = [pp, pp, ctypes.c_int, vp, vp]
         L.ntt_batch_forward.restype = ctypes.c_int
+        L.zk_microbench.argtypes = [ctypes.c_int, ctypes.c_uint32, vp, sz, vp, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]
+        L.zk_microbench.restype = ctypes.c_int
         L.zk_last_error.argtypes = []
         L.zk_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -182,6 +189,14 @@ def ntt_plan_resolve_opts(field, log2n: int, twiddle_mode: int = 0, log2_radix: 
     return _opts_dict(out)
 
 
+def ntt_plan_table_bytes(field, log2n: int, twiddle_mode: int = 0, log2_radix: int = 0, log2_tile: int = 0,
+                         flags: int = 0, log2_pass_radix: int = 0) -> int:
+    """Device bytes of the tables a plan would hold (host only; 0 if the
+    arguments are unsupported)."""
+    opts = _Opts(twiddle_mode, log2_radix, log2_tile, flags, log2_pass_radix)
+    return lib().ntt_plan_table_bytes(_field_id(field), log2n, ctypes.byref(opts))
+
+
 def ntt_plan_get_opts(plan: int) -> dict:
     out = _Opts()
     _check(lib().ntt_plan_get_opts(plan, ctypes.byref(out)), "ntt_plan_get_opts")
@@ -254,6 +269,10 @@ def ntt_forward(plan, d_in, d_out, d_work=None, stream=None) -> None:
     _transform("ntt_forward", plan, d_in, d_out, d_work, stream)
 
 
+def ntt_forward_noalloc(plan, d_in, d_out, stream=None) -> None:
+    _check(lib().ntt_forward_noalloc(plan, _ptr(d_in), _ptr(d_out), _stream(stream, d_in)), "ntt_forward_noalloc")
+
+
 def ntt_inverse(plan, d_in, d_out, d_work=None, stream=None) -> None:
     _transform("ntt_inverse", plan, d_in, d_out, d_work, stream)
 
@@ -296,6 +315,22 @@ def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -
     if rc < 0:
         _check(rc, "ntt_profile_passes")
     return [buf[k] for k in range(rc)]
+
+
+MICROBENCH = {"mad_u64_u32": 0, "fma_f64": 1, "add_u32": 2, "addc_u32": 3, "mad_addc": 4,
+              "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8}
+
+
+def zk_microbench(kind: str, d_buf, iters: int = 256, reps: int = 5, stream=None, buf_bytes: int | None = None):
+    """(rate per second, ms per launch) of one micro-benchmark kernel."""
+    ops, ms = ctypes.c_double(), ctypes.c_float()
+    if buf_bytes is None:
+        buf_bytes = d_buf.numel() * d_buf.element_size()
+    rc = lib().zk_microbench(MICROBENCH[kind], iters, _ptr(d_buf), buf_bytes, _stream(stream, d_buf), reps,
+                             ctypes.byref(ops), ctypes.byref(ms))
+    if rc != 0:
+        raise ZkError(rc, "zk_microbench", zk_last_error())
+    return ops.value, ms.value
 
 
 # ---------------------------------------------------------------------------

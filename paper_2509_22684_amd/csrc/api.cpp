@@ -491,6 +491,43 @@ int transform_entry(const ntt_plan* p, Kind kind, const void* in, void* out, voi
   return run_transform(p, kind, in, out, work, s);
 }
 
+// Workspace of ntt_forward_noalloc: a file-scope device array, so that the
+// call allocates nothing.  Each device holds its own copy at its own address;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (the array's name in host code is not a device address).
+constexpr uint64_t kNoAllocWorkElems = 1ull << 20;  // 32 MiB: ping-pong vector of n <= 2^20
+
+}  // namespace
+
+static __device__ __align__(256) Fe noalloc_scratch[kNoAllocWorkElems];
+
+namespace {
+
+struct ScratchAddrs {
+  std::mutex mu;
+  std::vector<void*> by_device;
+};
+ScratchAddrs& scratch_addrs() {
+  static ScratchAddrs* s = new ScratchAddrs();  // never destroyed
+  return *s;
+}
+
+// The scratch array's address on device `dev` (which must be current),
+// looked up once per device.
+int scratch_address(int dev, void** out) {
+  ScratchAddrs& sa = scratch_addrs();
+  std::lock_guard<std::mutex> lock(sa.mu);
+  if ((size_t)dev >= sa.by_device.size()) sa.by_device.resize((size_t)dev + 1, nullptr);
+  if (!sa.by_device[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(noalloc_scratch)");
+    sa.by_device[dev] = ptr;
+  }
+  *out = sa.by_device[dev];
+  return ZK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -565,6 +602,33 @@ int ntt_plan_resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* opts, 
   return resolve_opts(field, log2n, opts, resolved);
 }
 
+size_t ntt_plan_table_bytes(int field, uint32_t log2n, const ntt_plan_opts* opts) {
+  ntt_plan_opts o{};
+  if (resolve_opts(field, log2n, opts, &o) != ZK_OK) return 0;
+  // the allocations build_plan makes for this schedule
+  const std::vector<int> radices = split_passes(log2n, o.log2_pass_radix, o.log2_tile);
+  const int log_tile = log2n <= o.log2_tile ? (int)log2n : (int)o.log2_tile;
+  uint64_t elems = 0;
+  bool seen[33] = {false};
+  uint32_t log_ns = 0;
+  for (size_t k = 0; k < radices.size(); ++k) {
+    if (!zk::pass_shape_supported(radices[k], log_tile)) {
+      fail(ZK_EUNSUPPORTED, "no pass kernel for a radix-2^" + std::to_string(radices[k]) + " pass");
+      return 0;
+    }
+    if (!seen[radices[k]]) elems += 1ull << radices[k];
+    seen[radices[k]] = true;
+    if (k > 0 && o.twiddle_mode == 1) elems += (1ull << log_ns) << radices[k];
+    log_ns += (uint32_t)radices[k];
+  }
+  if (radices.size() > 1 && o.twiddle_mode == 2) {
+    const uint32_t log_lo = (log2n + 1) / 2;
+    elems += (1ull << log_lo) + (1ull << (log2n - log_lo));
+  }
+  elems += 3ull << log2n;  // coset tables
+  return elems * sizeof(Fe);
+}
+
 int ntt_plan_get_opts(const ntt_plan* p, ntt_plan_opts* out) {
   if (!p || !out) return fail(ZK_EINVAL, "null argument");
   *out = p->opts;
@@ -579,6 +643,19 @@ int ntt_plan_passes(const ntt_plan* p) { return p ? (int)p->passes.size() : 0; }
 
 int ntt_forward(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
   return transform_entry(p, kForward, d_in, d_out, d_work, stream);
+}
+
+int ntt_forward_noalloc(const ntt_plan* p, const void* d_in, void* d_out, void* stream) {
+  if (!p) return fail(ZK_EINVAL, "null plan");
+  if (workspace_elems(p) > kNoAllocWorkElems)
+    return fail(ZK_EUNSUPPORTED, "ntt_forward_noalloc holds a workspace of at most 2^20 elements (n <= 2^20); "
+                                 "this plan needs " + std::to_string(workspace_elems(p)));
+  void* work = nullptr;
+  if (workspace_elems(p)) {
+    if (int rc = check_device(p)) return rc;
+    if (int rc = scratch_address(p->device, &work)) return rc;
+  }
+  return transform_entry(p, kForward, d_in, d_out, work, stream);
 }
 
 int ntt_inverse(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
@@ -775,7 +852,10 @@ struct ntt_batch {
   uint32_t nitems = 0;
   uint32_t nq_end[3] = {0, 0, 0};  // end of each field's queues: BLS12-381, BN254, BLS12-377
   uint32_t grid = 0;
-  void* d_mem = nullptr;
+  void* d_mem = nullptr;  // descriptor block from the pool
+  size_t d_mem_bytes = 0;
+  hipEvent_t done_ev = nullptr;  // recorded on the launch stream after every launch
+  bool launched = false;
   zk::BatchJob* d_jobs = nullptr;
   zk::BatchItem* d_items = nullptr;
   zk::BatchQueue* d_queues = nullptr;
@@ -855,6 +935,69 @@ void give_back(int dev, const std::vector<hipStream_t>& streams, const std::vect
     if (x) sp.events.emplace_back(dev, x);
 }
 
+// Device memory for batch descriptors is recycled the same way: hipFree
+// waits for the whole device, so a serving loop that destroyed each tick's
+// batch with it would stall every stream of the device once per tick.
+// Blocks are powers of two from 64 KiB; a batch takes the smallest free
+// block that fits (one block per batch) and returns it on destruction.
+struct DescPool {
+  std::mutex mu;
+  struct Block {
+    int dev;
+    size_t bytes;
+    void* ptr;
+    hipEvent_t last_use;  // recorded after the last launch of the batch that held it, or null
+  };
+  std::vector<Block> free_blocks;
+};
+DescPool& desc_pool() {
+  static DescPool* pool = new DescPool();  // never destroyed: outlives every batch
+  return *pool;
+}
+
+size_t desc_block_bytes(size_t need) {
+  size_t b = 64 << 10;
+  while (b < need) b <<= 1;
+  return b;
+}
+
+hipError_t take_desc(int dev, size_t need, void** out, size_t* got) {
+  DescPool& dp = desc_pool();
+  const size_t want = desc_block_bytes(need);
+  {
+    std::lock_guard<std::mutex> lock(dp.mu);
+    size_t best = dp.free_blocks.size();
+    for (size_t i = 0; i < dp.free_blocks.size(); ++i) {
+      const DescPool::Block& bl = dp.free_blocks[i];
+      if (bl.dev == dev && bl.bytes >= want && (best == dp.free_blocks.size() || bl.bytes < dp.free_blocks[best].bytes))
+        best = i;
+    }
+    if (best < dp.free_blocks.size()) {
+      const DescPool::Block bl = dp.free_blocks[best];
+      dp.free_blocks.erase(dp.free_blocks.begin() + (long)best);
+      *out = bl.ptr;
+      *got = bl.bytes;
+      hipError_t e = hipSuccess;
+      if (bl.last_use) {
+        // the batch that held the block may still run if it was destroyed
+        // early; its descriptors are overwritten only once it is done
+        e = hipEventSynchronize(bl.last_use);
+        give_back(dev, {}, {bl.last_use});
+      }
+      return e;
+    }
+  }
+  *got = want;
+  return hipMalloc(out, want);
+}
+
+void give_desc(int dev, size_t bytes, void* ptr, hipEvent_t last_use) {
+  if (!ptr) return;
+  DescPool& dp = desc_pool();
+  std::lock_guard<std::mutex> lock(dp.mu);
+  dp.free_blocks.push_back(DescPool::Block{dev, bytes, ptr, last_use});
+}
+
 void free_batch(ntt_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -863,7 +1006,8 @@ void free_batch(ntt_batch* b) {
   std::vector<hipEvent_t> evs(b->joins);
   evs.push_back(b->fork_ev);
   give_back(b->device, b->sides, evs);
-  if (b->d_mem) (void)hipFree(b->d_mem);
+  give_desc(b->device, b->d_mem_bytes, b->d_mem, b->launched ? b->done_ev : nullptr);
+  if (!b->launched && b->done_ev) give_back(b->device, {}, {b->done_ev});
   delete b;
 }
 
@@ -1193,13 +1337,21 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       return hip_fail(e, "batch side streams");
     }
   }
+  e = take_event(dev, &b->done_ev);
+  if (e != hipSuccess) {
+    b->done_ev = nullptr;
+    free_batch(b);
+    return hip_fail(e, "batch event");
+  }
   const size_t jobs_bytes = ((sizeof(zk::BatchJob) * jobs.size() + 255) / 256) * 256;
   const size_t items_bytes = ((sizeof(zk::BatchItem) * items.size() + 255) / 256) * 256;
   const size_t queues_bytes = ((sizeof(zk::BatchQueue) * queues.size() + 255) / 256) * 256;
   const size_t ctl_words = zk::kCtlDone + (size_t)njobs * zk::kMaxBatchPasses;
   const size_t ctl_bytes = ((ctl_words * sizeof(uint32_t) + 255) / 256) * 256;
-  e = hipMalloc(&b->d_mem, jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t));
+  e = take_desc(dev, jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t),
+                &b->d_mem, &b->d_mem_bytes);
   if (e != hipSuccess) {
+    b->d_mem = nullptr;
     free_batch(b);
     return hip_fail(e, "hipMalloc(batch)");
   }
@@ -1296,16 +1448,27 @@ int ntt_batch_create_jobs(ntt_batch** out, const ntt_batch_job* jobs, int njobs,
   return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0, q ? q : kQueuesPerField);
 }
 
+// After every launch: the event that tells when the batch's descriptors
+// are free for reuse.
+int mark_launched(const ntt_batch* b, hipStream_t s) {
+  hipError_t e = hipEventRecord(b->done_ev, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(batch)");
+  const_cast<ntt_batch*>(b)->launched = true;
+  return ZK_OK;
+}
+
 int ntt_batch_launch(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
   if (!b->exec) return fail(ZK_EINVAL, "batch was created without a graph; use ntt_batch_launch_eager");
   hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? ZK_OK : hip_fail(e, "hipGraphLaunch(batch)");
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(batch)");
+  return mark_launched(b, static_cast<hipStream_t>(stream));
 }
 
 int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  return batch_enqueue(b, static_cast<hipStream_t>(stream));
+  if (int rc = batch_enqueue(b, static_cast<hipStream_t>(stream))) return rc;
+  return mark_launched(b, static_cast<hipStream_t>(stream));
 }
 
 int ntt_batch_status(const ntt_batch* b) {

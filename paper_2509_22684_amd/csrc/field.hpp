@@ -170,21 +170,26 @@ __device__ __forceinline__ uint64_t mad_co_vs(uint32_t a, uint32_t b, uint64_t c
   return r;
 }
 // Ordered (volatile) forms for mul_k: the compiler keeps volatile asm in
-// source order, which is how the K chains stay interleaved.
+// source order, which is how the K chains stay interleaved.  Each chain keeps
+// one SGPR pair for its carry mask for the whole product ("+s": the multiply-
+// add writes it, the carry add reads it and writes its own, unused, carry-out
+// back into it), so consecutive instructions of different chains never write
+// the same SGPRs: two VALU writes of one SGPR pair back to back need a wait
+// state on gfx950, which the compiler otherwise pays with an s_nop before
+// almost every instruction of the product.
 __device__ __forceinline__ uint64_t mad_co_vv_ord(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
   uint64_t r;
-  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "v"(b), "v"(c));
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "+s"(co) : "v"(a), "v"(b), "v"(c));
   return r;
 }
 __device__ __forceinline__ uint64_t mad_co_vs_ord(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
   uint64_t r;
-  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(co) : "v"(a), "s"(b), "v"(c));
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "+s"(co) : "v"(a), "s"(b), "v"(c));
   return r;
 }
-__device__ __forceinline__ uint32_t add_carry_ord(uint32_t x, uint64_t ci) {
+__device__ __forceinline__ uint32_t add_carry_ord(uint32_t x, uint64_t& co) {
   uint32_t r;
-  uint64_t unused;
-  asm volatile("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(unused) : "v"(x), "s"(ci));
+  asm volatile("v_addc_co_u32_e64 %0, %1, %2, 0, %1" : "=v"(r), "+s"(co) : "v"(x));
   return r;
 }
 // x + (carry bit of this lane)
@@ -260,6 +265,7 @@ __device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
   for (int k = 0; k < K; ++k) {
     acc[k] = 0;
     hi[k] = 0;
+    co[k] = 0;
   }
 #define ZK_TERMS(X, Y, MADFN)                                        \
   {                                                                  \

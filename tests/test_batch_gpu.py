@@ -98,6 +98,40 @@ def test_batch_graph_matches_oracle_and_per_launch(c4, cuda):
     batch.close()
 
 
+def test_bench_batch_schedule_matches_oracle(c4, cuda):
+    """The 64-job batch exactly as the benchmark builds and times it: plans
+    on the tuned batchable schedules (pass depth and twiddle source from the
+    tuning database), replayed from the graph several times, every job
+    against the oracle; then the same jobs on the tuned stand-alone
+    schedules, one launch sequence per job, byte-identical."""
+    import torch
+
+    from paper_2509_22684_amd import Batch, Plan
+    from paper_2509_22684_amd.autotune import tuned_opts
+
+    jobs, _, inputs, want = c4
+    plans, solo = {}, {}
+    for jb in jobs:
+        key = (jb.field, jb.log2n)
+        if key not in plans:
+            plans[key] = Plan(jb.field, jb.log2n, **tuned_opts(jb.field, jb.log2n, batchable=True))
+            solo[key] = Plan(jb.field, jb.log2n, **tuned_opts(jb.field, jb.log2n, batchable=False))
+    bufs = _fresh_bufs(inputs, cuda)
+    batch = Batch([plans[(j.field, j.log2n)] for j in jobs], bufs)
+    for rep in range(3):
+        _reset(bufs, inputs)
+        batch.launch()
+        torch.cuda.synchronize()
+        assert batch.status() == 0
+        _check_all(bufs, want, f"tuned batch replay {rep}")
+    per = _fresh_bufs(inputs, cuda)
+    for j, b in zip(jobs, per):
+        solo[(j.field, j.log2n)].forward(b, out=b)
+    torch.cuda.synchronize()
+    _check_all(per, want, "tuned per-launch")
+    batch.close()
+
+
 def test_batch_one_shot(c4, cuda):
     import torch
 

@@ -118,6 +118,23 @@ def test_quotient_small(cuda, field, log2n):
     _check(got, coracle.quotient(field, A, B, C), f"quotient {field} 2^{log2n}")
 
 
+@pytest.mark.parametrize("log2n", [19, pytest.param(22, marks=pytest.mark.slow)])
+def test_quotient_forked_chains_three_passes(cuda, log2n):
+    """Up to 2^22 quotient_poly runs A's and B's chains on forked streams;
+    from 2^19 each transform takes three passes.  The forked three-pass
+    path, which the serving baseline and the host pipeline time, against the
+    oracle element by element."""
+    from paper_2509_22684_amd import ntt_plan_passes
+
+    field = "bls12_381_fr"
+    n = 1 << log2n
+    A, B, C = (si.uniform_field_vector(field, n, si.stream_seed(23, log2n, v)) for v in range(3))
+    plan = _plan(field, log2n)
+    assert ntt_plan_passes(plan.handle) == 3
+    got = to_host(plan.quotient(to_dev(A, cuda), to_dev(B, cuda), to_dev(C, cuda)))
+    _check(got, coracle.quotient(field, A, B, C), f"forked quotient 2^{log2n}")
+
+
 @pytest.mark.parametrize("field,log2n", [("bls12_381_fr", 3), ("bn254_fr", 12), ("bls12_381_fr", 17)])
 def test_quotient_stages_compose(cuda, field, log2n):
     """quotient_coset_evals x3, quotient_pointwise and the coset inverse give
@@ -172,6 +189,71 @@ def test_error_codes(cuda):
     with pytest.raises(ZkError) as e:  # missing workspace
         ntt_forward(plan.handle, buf[:plan.n], buf[plan.n + 8:], None)
     assert e.value.code == -1
+
+
+def test_overlapping_buffers_are_refused(cuda):
+    """Aliasing is checked on byte ranges, not only base pointers."""
+    import torch
+
+    from paper_2509_22684_amd import ZkError, ntt_forward, quotient_poly, quotient_workspace_bytes
+
+    plan = _plan("bls12_381_fr", 14)
+    n = plan.n
+    big = torch.zeros(4 * n + 64, 8, dtype=torch.int32, device=cuda)
+    x, out = big[:n], big[n + 8:2 * n + 8]
+    with pytest.raises(ZkError) as e:  # workspace starts inside the output
+        ntt_forward(plan.handle, x, out, big[n + 16:])
+    assert e.value.code == -1
+    with pytest.raises(ZkError) as e:  # out overlaps in without being the same buffer
+        ntt_forward(plan.handle, x, big[8:], big[2 * n + 16:])
+    assert e.value.code == -1
+    qw = torch.zeros(quotient_workspace_bytes(plan.handle) // 32 + 8, 8, dtype=torch.int32, device=cuda)
+    A = big[:n]
+    with pytest.raises(ZkError) as e:  # H overlaps A's tail
+        quotient_poly(plan.handle, A, A, A, big[n - 8:], qw)
+    assert e.value.code == -1
+
+
+def test_validate_refused_under_capture(cuda):
+    """ZK_FLAG_VALIDATE reads its count back to the host, so a call on a
+    stream being captured is refused instead of breaking the capture."""
+    import torch
+
+    from paper_2509_22684_amd import Plan, ZkError
+
+    plan = Plan("bls12_381_fr", 10, flags=1)
+    x = to_dev(si.uniform_field_vector("bls12_381_fr", 1 << 10, 6), cuda)
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream(cuda)
+    g = torch.cuda.CUDAGraph()
+    raised = None
+    with torch.cuda.graph(g, stream=s):
+        try:
+            plan.forward(x, y, stream=s)
+        except ZkError as e:
+            raised = e
+    assert raised is not None and raised.code == -1 and "capture" in str(raised)
+
+
+@pytest.mark.parametrize("log2n,opts", [(10, {}), (16, {}), (20, {}), (24, {}), (20, dict(twiddle_mode=2)),
+                                        (18, dict(log2_pass_radix=6)), (21, dict(log2_tile=11))])
+def test_plan_table_bytes_matches_the_plan(cuda, log2n, opts):
+    """The host-side size query equals what the created plan holds."""
+    from paper_2509_22684_amd import ntt_plan_device_bytes, ntt_plan_table_bytes
+
+    plan = _plan("bls12_381_fr", log2n, **opts)
+    assert ntt_plan_table_bytes("bls12_381_fr", log2n, **opts) == ntt_plan_device_bytes(plan.handle) > 0
+
+
+def test_default_plan_runs_the_registered_tuned_schedule(cuda):
+    """Plan() with zero options registers the tuning database for this device
+    and resolves its schedule through it."""
+    from paper_2509_22684_amd import _lib, ntt_plan_resolve_opts
+
+    for log2n in (16, 20, 24):
+        plan = _plan("bls12_381_fr", log2n)
+        assert plan.opts == ntt_plan_resolve_opts("bls12_381_fr", log2n)
+    assert _lib._tuning_loaded
 
 
 def test_validate_flag_rejects_noncanonical(cuda):

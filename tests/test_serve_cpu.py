@@ -1,6 +1,7 @@
 """Scheduling logic of the quotient server on the CPU, with an executor backed
 by the oracle (no GPU): admission by memory budget, FIFO waiting, rejection
-of jobs larger than the budget, continuous batching across ticks, and that
+of jobs larger than the budget or of unsupported sizes, ticks enqueued ahead
+without waiting, lanes by size, continuous batching across ticks, and that
 every finished job carries the oracle's quotient."""
 import numpy as np
 
@@ -13,28 +14,63 @@ FIELD = "bls12_381_fr"
 
 class OracleExecutor:
     """Executor with the GpuExecutor interface that computes each finished
-    job's quotient with the C oracle and records every tick."""
+    job's quotient with the C oracle and records every tick.  Ticks complete
+    when `complete_after` polls have seen them (0: at once)."""
 
-    def __init__(self, plan_bytes_per_elem=32):
+    def __init__(self, plan_bytes_per_elem=32, lane_bounds=(), complete_after=0):
         self.ticks = []
+        self.lane_ticks = []
         self.pb = plan_bytes_per_elem
+        self.lane_bounds = tuple(lane_bounds)
+        self.complete_after = complete_after
+        self.allocations = 0
+        self.plans = set()
+        self.tokens = []
+        self.max_open_at_enqueue = 0  # ticks launched and not yet complete when another is launched
+
+    @property
+    def lanes(self):
+        return len(self.lane_bounds) + 1
+
+    def lane_of(self, log2n):
+        return sum(log2n > b for b in self.lane_bounds)
+
+    @staticmethod
+    def supports(log2n):
+        return 2 <= log2n <= 32
 
     def plan_bytes(self, log2n):
-        return self.pb << log2n
+        return self.pb << log2n  # a formula: no plan is built to learn it
 
     @staticmethod
     def job_bytes(log2n):
         return 9 * 32 << log2n
 
     def admit(self, req):
+        self.plans.add(req.log2n)
+        self.allocations += 1
         return {"req": req}
 
-    def run_tick(self, items):
+    def enqueue_tick(self, lane, items):
         self.ticks.append([(h["req"].job_id, stage) for h, stage in items])
+        self.lane_ticks.append(lane)
         for h, stage in items:
+            assert self.lane_of(h["req"].log2n) == lane
             if stage == STAGES - 1:
                 A, B, C = h["req"].inputs
                 h["H"] = coracle.quotient(FIELD, A, B, C, threads=2)
+        open_ticks = sum(t["polls"] <= self.complete_after for t in self.tokens)
+        self.max_open_at_enqueue = max(self.max_open_at_enqueue, open_ticks)
+        token = {"polls": 0}
+        self.tokens.append(token)
+        return token
+
+    def tick_done(self, token):
+        token["polls"] += 1
+        return token["polls"] > self.complete_after
+
+    def finish_tick(self, token):
+        pass
 
     def result(self, h):
         return h["H"]
@@ -72,6 +108,24 @@ def test_all_jobs_finish_with_oracle_results_and_share_ticks():
     assert s["done"] == 5 and s["rejected"] == 0
 
 
+def test_ticks_are_enqueued_ahead_of_completion():
+    """With depth 2 the next stage is launched before the current tick has
+    completed: the host never waits for a tick to build the next one."""
+    reqs = make_requests([5, 5])
+    ex = OracleExecutor(complete_after=3)
+    srv = QuotientServer(ex, budget_bytes=1 << 30, depth=2, poll_s=0)
+    res = srv.run(reqs, realtime=False)
+    check_results(res, reqs)
+    assert [sorted(st for _, st in t) for t in ex.ticks] == [[s, s] for s in range(STAGES)]
+    assert ex.max_open_at_enqueue == 1
+    # depth 1: same ticks, each enqueued only after the previous completed
+    ex1 = OracleExecutor(complete_after=3)
+    res1 = QuotientServer(ex1, budget_bytes=1 << 30, depth=1, poll_s=0).run(reqs, realtime=False)
+    check_results(res1, reqs)
+    assert ex1.ticks == ex.ticks
+    assert ex1.max_open_at_enqueue == 0
+
+
 def test_tiny_budget_serialises_jobs():
     reqs = make_requests([5, 5, 5])
     ex = OracleExecutor()
@@ -84,14 +138,32 @@ def test_tiny_budget_serialises_jobs():
     assert srv.peak_bytes <= one_job
 
 
-def test_oversize_job_rejected_others_served():
-    reqs = make_requests([4, 9, 4])
+def test_oversize_and_unsupported_jobs_rejected_others_served():
+    reqs = make_requests([4, 9, 4, 4])
+    reqs[3] = Request(3, 40, 0.0, reqs[0].inputs)  # beyond the field's 2-adicity
     ex = OracleExecutor()
     budget = ex.job_bytes(6) + ex.plan_bytes(4) + ex.plan_bytes(6)
     srv = QuotientServer(ex, budget_bytes=budget)
     res = srv.run(reqs, realtime=False)
-    assert [r.status for r in res] == ["done", "rejected", "done"]
+    assert [r.status for r in res] == ["done", "rejected", "done", "rejected"]
     check_results([res[0], res[2]], [reqs[0], reqs[2]])
+    # a rejected size never got a plan or a buffer
+    assert ex.plans == {4} and ex.allocations == 2
+
+
+def test_lanes_by_size_tick_independently():
+    """Small and large jobs go to different lanes; each lane's ticks hold
+    only its own jobs, and a lane with a slow tick does not hold the other."""
+    reqs = make_requests([4, 8, 4, 8])
+    ex = OracleExecutor(lane_bounds=(6,))
+    srv = QuotientServer(ex, budget_bytes=1 << 30)
+    res = srv.run(reqs, realtime=False)
+    check_results(res, reqs)
+    small = [t for t, ln in zip(ex.ticks, ex.lane_ticks) if ln == 0]
+    large = [t for t, ln in zip(ex.ticks, ex.lane_ticks) if ln == 1]
+    assert len(small) == STAGES and len(large) == STAGES
+    assert all({j for j, _ in t} == {0, 2} for t in small)
+    assert all({j for j, _ in t} == {1, 3} for t in large)
 
 
 def test_jobs_join_in_flight_batches():
@@ -109,9 +181,9 @@ def test_jobs_join_in_flight_batches():
     reqs = make_requests([5, 5], gaps=[1.5, 0.0])  # second job arrives at t = 1.5
 
     class TickingExecutor(OracleExecutor):
-        def run_tick(self, items):
-            super().run_tick(items)
+        def enqueue_tick(self, lane, items):
             clock.t += 1.0  # each tick takes one time unit
+            return super().enqueue_tick(lane, items)
 
     ex = TickingExecutor()
     srv = QuotientServer(ex, budget_bytes=1 << 30, clock=clock)
@@ -122,3 +194,11 @@ def test_jobs_join_in_flight_batches():
     stages_in_mixed = {tuple(sorted(t)) for t in mixed}
     assert any(dict(t)[0] != dict(t)[1] for t in stages_in_mixed), "jobs at different stages share a launch"
     assert res[1].admit_s >= reqs[1].arrival_s
+
+
+def test_summary_slowdown_against_solo():
+    reqs = make_requests([4, 5])
+    ex = OracleExecutor()
+    res = QuotientServer(ex, budget_bytes=1 << 30).run(reqs, realtime=False)
+    s = summarize(res, solo_s={4: 1.0, 5: 1.0})
+    assert s["p50_slowdown"] >= 0 and set(s["by_log2n"]) == {"4", "5"}

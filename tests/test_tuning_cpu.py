@@ -83,3 +83,16 @@ def test_bad_registrations_and_arguments_are_refused():
     assert L.ntt_plan_resolve_opts(1, 20, None, out) == 0
     assert L.ntt_plan_get_opts(None, out) == -1
     assert os.path.exists(_lib.LIB_PATH)
+
+
+def test_plan_table_bytes_on_the_host():
+    """Table bytes of the 2^24 plan: w_256 (256 entries), the second pass's
+    [r][j mod 256] table (2^16), the third pass's (2^24) and three coset
+    tables (3 x 2^24), 32 bytes each; unsupported sizes give 0."""
+    n = 1 << 24
+    assert _lib.ntt_plan_table_bytes("bls12_381_fr", 24) == 32 * (256 + (1 << 16) + n + 3 * n)
+    assert _lib.ntt_plan_table_bytes("bls12_381_fr", 33) == 0
+    assert _lib.ntt_plan_table_bytes("bn254_fr", 10) == 32 * ((1 << 10) + 3 * (1 << 10))
+    two = _lib.ntt_plan_table_bytes("bls12_381_fr", 20, twiddle_mode=2)
+    one = _lib.ntt_plan_table_bytes("bls12_381_fr", 20, twiddle_mode=1)
+    assert 0 < two < one
