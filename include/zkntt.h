@@ -76,8 +76,9 @@ typedef struct {
   uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (1, radix-2, up to
                                n = 2^18; 2 above), 1 (radix-2), 2 or 3 */
   uint32_t log2_tile;       /* elements per workgroup tile of a multi-pass transform, log2:
-                               0 default (10), 10 or 11 (2^11 tiles: twice the LDS, half the
-                               workgroups per CU) */
+                               0 default (10), 8 (small transforms over more CUs; register radix
+                               2 or 4 only, passes of at most 2^7 points), 10 or 11 (2^11 tiles:
+                               twice the LDS, half the workgroups per CU) */
   uint32_t flags;           /* ZK_FLAG_* */
   uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (9 up to
                                n = 2^18, so at most two passes there; 8 above), 4..9 */
@@ -324,6 +325,8 @@ int ntt_profile_passes(const ntt_plan *p, int kind, const void *d_in, void *d_ou
  *   ZK_MB_FFMUL_BLS12_381  Montgomery products/s over BLS12-381 Fr (three interleaved per thread,
  *                          four waves per SIMD, like the pass kernels); ZK_MB_FFMUL_K2 and
  *                          ZK_MB_FFMUL_K4 interleave two and four
+ *   ZK_MB_MAD_FMA          instructions/s of v_mad_u64_u32 and v_fma_f64 interleaved (independent)
+ *   ZK_MB_MAD_ADD          instructions/s of v_mad_u64_u32 and v_add_u32 interleaved (independent)
  *   ZK_MB_COPY             bytes/s read plus written by a streaming copy of the
  *                          first half of d_buf into its second half
  * `iters`: loop trips per thread (ALU kinds; ignored by the copy).  d_buf:
@@ -340,7 +343,9 @@ typedef enum {
   ZK_MB_FFMUL_BLS12_381 = 5,
   ZK_MB_COPY = 6,
   ZK_MB_FFMUL_K2 = 7,
-  ZK_MB_FFMUL_K4 = 8
+  ZK_MB_FFMUL_K4 = 8,
+  ZK_MB_MAD_FMA = 9,
+  ZK_MB_MAD_ADD = 10
 } zk_microbench_kind;
 int zk_microbench(int kind, uint32_t iters, void *d_buf, size_t buf_bytes, void *stream, int reps,
                   double *ops_per_s, float *ms_per_launch);

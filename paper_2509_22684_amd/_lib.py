@@ -318,7 +318,7 @@ def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -
 
 
 MICROBENCH = {"mad_u64_u32": 0, "fma_f64": 1, "add_u32": 2, "addc_u32": 3, "mad_addc": 4,
-              "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8}
+              "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8, "mad_fma": 9, "mad_add": 10}
 
 
 def zk_microbench(kind: str, d_buf, iters: int = 256, reps: int = 5, stream=None, buf_bytes: int | None = None):

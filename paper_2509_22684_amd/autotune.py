@@ -40,8 +40,10 @@ def candidates(log2n: int, batchable: bool = False) -> list[dict]:
         return [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm) for pr in (6, 7, 8, 9) for tm in (1, 2)]
     out = [dict(log2_radix=2, log2_pass_radix=pr, twiddle_mode=tm, log2_tile=tile)
            for pr in (6, 7, 8, 9) for tm in (1, 2) for tile in (11, 10)]
-    if not batchable:  # radix-2 and radix-8 register rounds on the default split
-        out += [dict(log2_radix=1), dict(log2_radix=3)]
+    # radix-2 and radix-8 register rounds on the default split
+    out += [dict(log2_radix=1), dict(log2_radix=3)]
+    if log2n <= 16:  # small transforms: 2^8-element tiles spread a pass over more CUs
+        out += [dict(log2_radix=e, log2_tile=8) for e in (1, 2)]
     return out
 
 

@@ -187,6 +187,8 @@ std::vector<int> split_passes(uint32_t log_n, uint32_t max_log_r, uint32_t log_t
     r.push_back((int)log_n);
     return r;
   }
+  // a column of a multi-pass tile holds fewer points than the tile
+  max_log_r = std::min(max_log_r, log_tile - 1);
   const int P = (int)((log_n + max_log_r - 1) / max_log_r);
   const int base = (int)log_n / P, extra = (int)log_n % P;
   for (int k = 0; k < P; ++k) r.push_back(base + (k < extra ? 1 : 0));
@@ -216,7 +218,7 @@ int build_plan(ntt_plan* p) {
     d.log_r = radices[k];
     d.log_tile = (L <= p->log_tile) ? (int)L : (int)p->log_tile;
     d.log_ns = log_ns;
-    if (!zk::pass_shape_supported(d.log_r, d.log_tile))
+    if (!zk::pass_shape_supported(d.log_r, d.log_tile, p->log_e))
       return fail(ZK_EUNSUPPORTED, "no pass kernel for a radix-2^" + std::to_string(d.log_r) +
                                        " pass; choose a larger log2_pass_radix");
     if (!tw_r_by_log[d.log_r]) {
@@ -297,8 +299,8 @@ int check_opts(const ntt_plan_opts& o) {
   if (o.log2_pass_radix && (o.log2_pass_radix < 4 || o.log2_pass_radix > 9))
     return fail(ZK_EUNSUPPORTED, "log2_pass_radix must be 0 or 4..9");
   if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
-  if (!(o.log2_tile == 0 || o.log2_tile == 10 || o.log2_tile == 11))
-    return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 10 or 11");
+  if (!(o.log2_tile == 0 || o.log2_tile == 8 || o.log2_tile == 10 || o.log2_tile == 11))
+    return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 8, 10 or 11");
   if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
   return ZK_OK;
 }
@@ -338,6 +340,8 @@ int resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* in, ntt_plan_op
   if (!o.log2_radix) o.log2_radix = log2n <= 18 ? 1 : 2;
   if (!o.log2_tile) o.log2_tile = 10;
   if (!o.log2_pass_radix) o.log2_pass_radix = log2n <= 18 ? 9 : 8;
+  if (o.log2_tile == 8 && o.log2_radix == 3 && log2n > 8)
+    return fail(ZK_EUNSUPPORTED, "2^8-element tiles take two or four elements per thread (log2_radix 1 or 2)");
   *out = o;
   return ZK_OK;
 }
@@ -612,7 +616,7 @@ size_t ntt_plan_table_bytes(int field, uint32_t log2n, const ntt_plan_opts* opts
   bool seen[33] = {false};
   uint32_t log_ns = 0;
   for (size_t k = 0; k < radices.size(); ++k) {
-    if (!zk::pass_shape_supported(radices[k], log_tile)) {
+    if (!zk::pass_shape_supported(radices[k], log_tile, (int)o.log2_radix)) {
       fail(ZK_EUNSUPPORTED, "no pass kernel for a radix-2^" + std::to_string(radices[k]) + " pass");
       return 0;
     }

@@ -63,6 +63,14 @@ __global__ void __launch_bounds__(kThreads) rate_kernel(uint32_t iters, uint32_t
           // one FIPS column step: acc += a b with its carry-out counted
           asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc[k]), "+s"(co[k]) : "v"(a), "v"(b));
           asm volatile("v_addc_co_u32_e64 %0, %1, %0, 0, %1" : "+v"(lo[k]), "+s"(co[k]));
+        } else if constexpr (KIND == ZK_MB_MAD_FMA) {
+          // an integer multiply-add and an independent FP64 FMA: whether the
+          // two share one issue slot or can run side by side
+          asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc[k]), "+s"(co[k]) : "v"(a), "v"(b));
+          asm volatile("v_fma_f64 %0, %1, %2, %0" : "+v"(d[k]) : "v"(x), "v"(y));
+        } else if constexpr (KIND == ZK_MB_MAD_ADD) {
+          asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc[k]), "+s"(co[k]) : "v"(a), "v"(b));
+          asm volatile("v_add_u32 %0, %1, %0" : "+v"(lo[k]) : "v"(a));
         }
       }
     }
@@ -141,6 +149,12 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       case ZK_MB_MAD_ADDC:
         hipLaunchKernelGGL(rate_kernel<ZK_MB_MAD_ADDC>, dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
         break;
+      case ZK_MB_MAD_FMA:
+        hipLaunchKernelGGL(rate_kernel<ZK_MB_MAD_FMA>, dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
+        break;
+      case ZK_MB_MAD_ADD:
+        hipLaunchKernelGGL(rate_kernel<ZK_MB_MAD_ADD>, dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
+        break;
       case ZK_MB_FFMUL_BLS12_381:
         hipLaunchKernelGGL((ffmul_kernel<Bls12_381Fr, 3>), dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
         break;
@@ -170,7 +184,9 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       ops = (double)lanes * iters * kUnroll * kChains;  // instructions (MAD+ADDC: column steps)
       break;
     case ZK_MB_ADDC_U32:
-      ops = (double)lanes * iters * kUnroll * kChains * 2;  // v_add_co + v_addc_co
+    case ZK_MB_MAD_FMA:
+    case ZK_MB_MAD_ADD:
+      ops = (double)lanes * iters * kUnroll * kChains * 2;  // two instructions per step
       break;
     case ZK_MB_FFMUL_BLS12_381:
       ops = (double)lanes * iters * 3;

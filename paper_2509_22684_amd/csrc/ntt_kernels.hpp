@@ -53,11 +53,13 @@ struct PassArgs {
 };
 
 // Shapes the pass kernels are instantiated for: tiles of 2^10 or 2^11
-// elements with 2^3 .. 2^9 points per column, or one tile holding a whole
-// transform of up to 2^11 points.
-inline bool pass_shape_supported(int log_r, int log_tile) {
+// elements with 2^3 .. 2^9 points per column, tiles of 2^8 elements with
+// 2^3 .. 2^7 points per column (two or four elements per thread only), or
+// one tile holding a whole transform of up to 2^11 points.
+inline bool pass_shape_supported(int log_r, int log_tile, int log_e = 2) {
   if (log_tile == 11) return (log_r >= 3 && log_r <= 9) || log_r == 11;
   if (log_tile == 10 && log_r >= 3 && log_r <= 9) return true;
+  if (log_tile == 8 && log_r >= 3 && log_r <= 7 && log_e <= 2) return true;
   return log_tile == log_r && log_r >= 0 && log_r <= 10;
 }
 

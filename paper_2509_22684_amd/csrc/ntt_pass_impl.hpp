@@ -413,11 +413,25 @@ hipError_t launch_one(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Multi-pass tiles of 2^11 or 2^10 elements with radix 2^3 .. 2^9 per pass, and
-// single-pass transforms of up to 2^11 points held in one tile.  Keep in step
-// with pass_shape_supported().
+// Multi-pass tiles of 2^11 or 2^10 elements with radix 2^3 .. 2^9 per pass,
+// 2^8-element tiles with radix 2^3 .. 2^8 for two or four elements per
+// thread (small transforms spread over more CUs), and single-pass transforms
+// of up to 2^11 points held in one tile.  Keep in step with
+// pass_shape_supported().
 template <class F, int LOG_E>
 hipError_t dispatch_shape(int log_r, int log_tile, const PassArgs& a, hipStream_t s) {
+  if constexpr (LOG_E <= 2) {
+    if (log_tile == 8 && log_r < 8) {
+      switch (log_r) {
+        case 3: return launch_one<F, 3, 8, LOG_E>(a, s);
+        case 4: return launch_one<F, 4, 8, LOG_E>(a, s);
+        case 5: return launch_one<F, 5, 8, LOG_E>(a, s);
+        case 6: return launch_one<F, 6, 8, LOG_E>(a, s);
+        case 7: return launch_one<F, 7, 8, LOG_E>(a, s);
+        default: break;
+      }
+    }
+  }
   if (log_tile == 10 && log_r < 10) {
     switch (log_r) {
       case 3: return launch_one<F, 3, 10, LOG_E>(a, s);

@@ -219,7 +219,7 @@ def test_batch_small_jobs(cuda, log2n):
 
 
 @pytest.mark.parametrize("opts", [dict(log2_radix=1), dict(log2_radix=3), dict(log2_pass_radix=6, twiddle_mode=2),
-                                  dict(log2_pass_radix=7, twiddle_mode=1)])
+                                  dict(log2_pass_radix=7, twiddle_mode=1), dict(log2_tile=8, log2_radix=1)])
 def test_batch_other_schedules(cuda, opts):
     """Plans built with other schedules batch too: the batch kernel runs each
     plan's own pass split and twiddle source, so every job still equals the
@@ -408,7 +408,8 @@ def test_batch_grouped_launches_every_kind(cuda, log2n):
 
 
 @pytest.mark.parametrize("opts", [dict(twiddle_mode=2), dict(log2_pass_radix=6), dict(log2_radix=3),
-                                  dict(log2_radix=1), dict(log2_pass_radix=7, twiddle_mode=2)])
+                                  dict(log2_radix=1), dict(log2_pass_radix=7, twiddle_mode=2),
+                                  dict(log2_tile=8, log2_radix=1)])
 def test_batch_grouped_launches_other_schedules(cuda, opts):
     """Grouped launches run the plans' pass split, tile and twiddle source
     with radix-4 register rounds whatever the plans' register radix; eight

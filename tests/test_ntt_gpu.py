@@ -277,8 +277,10 @@ def test_validate_flag_rejects_noncanonical(cuda):
                                   dict(log2_tile=10, log2_radix=3), dict(log2_tile=10, log2_radix=1),
                                   dict(log2_pass_radix=8), dict(log2_pass_radix=9), dict(log2_pass_radix=9, log2_tile=11),
                                   dict(log2_pass_radix=9, twiddle_mode=2), dict(log2_pass_radix=9, log2_radix=3),
-                                  dict(log2_pass_radix=9, log2_radix=1)])
-@pytest.mark.parametrize("log2n", [11, 12, 17, 18, 20])
+                                  dict(log2_pass_radix=9, log2_radix=1), dict(log2_tile=8, log2_radix=1),
+                                  dict(log2_tile=8, log2_radix=2), dict(log2_tile=8, log2_radix=1, twiddle_mode=2),
+                                  dict(log2_tile=8, log2_radix=2, log2_pass_radix=5)])
+@pytest.mark.parametrize("log2n", [8, 9, 11, 12, 17, 18, 20])
 def test_schedules_are_byte_identical(cuda, opts, log2n):
     """Every schedule the autotuner may pick (pass fusion depth, twiddle
     source) gives the oracle's bytes for all four transforms."""
