@@ -101,7 +101,7 @@ def peaks_leg(dev) -> dict:
     out = {}
     for kind, iters in (("mad_u64_u32", 2048), ("fma_f64", 2048), ("add_u32", 2048), ("addc_u32", 1024),
                         ("mad_addc", 1024), ("mad_fma", 1024), ("mad_add", 1024), ("ffmul_bls12_381", 128),
-                        ("ffmul_k2", 192), ("ffmul_k4", 96)):
+                        ("ffmul_k2", 192), ("ffmul_k4", 96), ("ffmul_f64", 96)):
         rate, ms = zk_microbench(kind, small, iters=iters, reps=5)
         out[kind] = {"per_s": rate, "ms_per_launch": ms, "iters": iters}
     big = torch.empty(1 << 26, 8, dtype=torch.int32, device=dev)  # 2 GiB: 1 GiB read, 1 GiB written
@@ -118,7 +118,7 @@ def peaks_leg(dev) -> dict:
         "fips_column_steps_T_per_s": out["mad_addc"]["per_s"] / 1e12,
         "mad_with_fma_f64_T_instr_per_s": out["mad_fma"]["per_s"] / 1e12,
         "mad_with_add_u32_T_instr_per_s": out["mad_add"]["per_s"] / 1e12,
-        "ffmul_G_per_s": {k: out[f"ffmul_{k}"]["per_s"] / 1e9 for k in ("bls12_381", "k2", "k4")},
+        "ffmul_G_per_s": {k: out[f"ffmul_{k}"]["per_s"] / 1e9 for k in ("bls12_381", "k2", "k4", "f64")},
         "hbm_copy_TB_per_s": out["copy"]["bytes_per_s"] / 1e12,
         "spec_issue_rate_T_per_s": spec / 1e12,
     }
@@ -331,6 +331,58 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0, 1.25, 1.5)) -> dict:
             "runs": runs, "admission_2GB": admission}
 
 
+def msm_leg(dev, log2n: int = 20, reps: int = 10) -> dict:
+    """MSM on BLS12-381 G1 (the paper's other proving kernel): n = 2^20 fixed
+    bases P_i = (i + 1) G, G a point of the order-r subgroup, with their
+    per-window multiples precomputed once (timed separately), and uniform
+    scalars (Montgomery Fr limbs, as the NTT produces them).  The result is
+    checked against the closed form (sum_i s_i (i + 1)) G from the oracle."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from oracle import msm_ref as M
+    from oracle import ref
+    from paper_2509_22684_amd import MsmBases
+
+    n = 1 << log2n
+    G = M.subgroup_point(7)
+    t0 = time.perf_counter()
+    pts = M.multiples(G, n)
+    gen_s = time.perf_counter() - t0
+    d_pts = torch.from_numpy(M.points_to_device_layout(pts).view(np.int32)).to(dev)
+    sc = si.uniform_field_vector(FIELD, n, si.stream_seed(8, 0, 0))
+    d_sc = torch.from_numpy(sc.view(np.int32)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bases = MsmBases(d_pts)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    res = torch.empty(64, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        bases.msm(d_sc, res)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        bases.msm(d_sc, res)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    words = res.cpu().numpy().view(np.uint32)[:48]
+    X, Y, ZZ, ZZZ = (M.fq_from_limbs(words[12 * k:12 * (k + 1)].reshape(1, 12))[0] for k in range(4))
+    FR = ref.BLS12_381_FR
+    s_plain = FR.from_mont(si.limbs_to_ints(sc))
+    want = M.mul(sum(v * (i + 1) for i, v in enumerate(s_plain)) % FR.p, G)
+    c = bases.window_bits
+    windows = (255 + c - 1) // c
+    return {"workload": f"MSM over BLS12-381 G1, n=2^{log2n} fixed bases (i+1)G, uniform scalars (seed 8)",
+            "ms": ms, "points_per_s": n / (ms * 1e-3), "window_bits": c, "windows": windows,
+            "mixed_additions": n * windows, "precompute_s": setup_s, "table_bytes": bases.device_bytes,
+            "host_point_generation_s": gen_s, "matches_closed_form": M.xyzz_to_affine(X, Y, ZZ, ZZZ) == want}
+
+
 def host_pipeline_leg(dev, log2n: int = 22, njobs: int = 8) -> dict:
     """Quotient jobs whose A, B, C start in pinned host memory and whose H
     returns there: one job at a time with nothing overlapped, against the
@@ -410,7 +462,9 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the host-resident pipeline leg")
-    ap.add_argument("--only", choices=["forward", "copy", "batch", "quotient", "peaks", "serve"], default=None,
+    ap.add_argument("--no-msm", action="store_true", help="skip the MSM leg")
+    ap.add_argument("--only", choices=["forward", "copy", "batch", "quotient", "peaks", "serve", "msm"],
+                    default=None,
                     help="for profiler runs: only run --steps forward NTTs at 2^24, --steps plain device "
                          "copies of one 512 MiB vector (the traffic calibration kernel), --warmup + --steps "
                          "graph replays of the 64-job batch, or --warmup + --steps quotient chains at 2^24 "
@@ -434,6 +488,10 @@ def main() -> int:
     def to_dev(a):
         return torch.from_numpy(np.ascontiguousarray(a).view(np.int32).copy()).to(dev)
 
+    if args.only == "msm":
+        print(json.dumps(msm_leg(dev, reps=max(1, args.steps))), flush=True)
+        print("[bench] msm leg done", file=sys.stderr, flush=True)
+        return 0
     if args.only == "serve":
         print(json.dumps(serve_leg(dev)), flush=True)
         print("[bench] serving leg done", file=sys.stderr, flush=True)
@@ -623,6 +681,9 @@ def main() -> int:
     if not args.no_pipeline:
         print("[bench] host-resident quotient pipeline", file=sys.stderr, flush=True)
         result["host_pipeline"] = host_pipeline_leg(dev)
+    if not args.no_msm:
+        print("[bench] MSM (BLS12-381 G1, n = 2^20)", file=sys.stderr, flush=True)
+        result["msm"] = msm_leg(dev)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(host[0])

@@ -86,6 +86,12 @@ typedef struct {
 
 #define ZK_FLAG_VALIDATE 1u /* check that inputs are canonical (adds a device-to-host sync, so calls on a
                                stream that is being captured into a graph return ZK_EINVAL) */
+#define ZK_FLAG_FFMUL_FP64 2u /* every product of the transforms on the FP64 units (v_fma_f64, 48-bit
+                                 limbs, error-free product transformations) instead of v_mad_u64_u32:
+                                 the paper's open question of using the floating-point pipes for FF_mul
+                                 (Sections IV-B, V-C).  Same bytes.  BLS12-381 Fr, radix-4 register
+                                 rounds, ntt_forward / ntt_inverse / ntt_coset_* only (the quotient
+                                 calls and batches return ZK_EUNSUPPORTED on such a plan). */
 
 /* Create a plan for n = 2^log2n transforms over `field` on the current HIP
  * device: derives the root of unity and builds its twiddle and coset tables
@@ -313,6 +319,45 @@ int ntt_batch_forward(const ntt_plan *const *plans, void *const *d_bufs, int njo
 int ntt_profile_passes(const ntt_plan *p, int kind, const void *d_in, void *d_out, void *d_work, void *stream,
                        float *ms_per_pass, int max_passes);
 
+/* ------------------------------------------------------------------------
+ * Multi-scalar multiplication on BLS12-381 G1: Q = sum_i s_i P_i, the
+ * paper's other dominant proving kernel (Section II-A, Fig. 4(a); Table V
+ * counts its point operations).  Pippenger's bucket method with XYZZ
+ * accumulators, over fixed bases (the proving key's points) whose per-window
+ * multiples are precomputed once.
+ *
+ * Layouts (device memory, 256-byte aligned):
+ *   - a point: 24 32-bit limbs, x then y, each 12 little-endian limbs of the
+ *     Montgomery form v 2^384 mod q (q the 381-bit base field prime), affine,
+ *     canonical; the bases must lie in the order-r subgroup (r the BLS12-381
+ *     scalar field modulus), not at infinity;
+ *   - a scalar: 8 limbs, the Montgomery form s 2^256 mod r over BLS12-381 Fr,
+ *     as every NTT call of this library reads and writes them (so an NTT or
+ *     quotient output feeds an MSM directly);
+ *   - the result: 48 limbs, XYZZ coordinates (X, Y, ZZ, ZZZ) in the same
+ *     Montgomery form with x = X / ZZ and y = Y / ZZZ; ZZ = 0 is the point at
+ *     infinity.  (Affine coordinates would need one field inversion, a serial
+ *     chain the caller can run wherever it likes.)
+ * ------------------------------------------------------------------------ */
+typedef struct msm_bases msm_bases;
+
+/* Precompute, for c-bit windows w < W = ceil(255 / c), the multiples
+ * 2^(c w) P_i of the n points (W n affine points of device memory, held by
+ * the bases); window_bits = c, 0 = chosen from n (16 from n = 2^18).
+ * Synchronous (waits for `stream`).  ZK_EINVAL: null, misaligned or n = 0;
+ * ZK_EUNSUPPORTED: window_bits > 16 or W n >= 2^32. */
+int msm_bases_create(msm_bases **out, const void *d_points, uint64_t n, uint32_t window_bits, void *stream);
+void msm_bases_destroy(msm_bases *b);
+uint64_t msm_bases_count(const msm_bases *b);
+int msm_bases_window_bits(const msm_bases *b);
+size_t msm_bases_device_bytes(const msm_bases *b);
+/* Bytes of workspace msm_compute needs (sort arrays and bucket sums). */
+size_t msm_workspace_bytes(const msm_bases *b);
+/* d_result = sum_i s_i P_i for the n scalars at d_scalars; asynchronous on
+ * `stream`.  d_work: msm_workspace_bytes(b) bytes; concurrent calls need
+ * their own workspace.  Inputs are not modified. */
+int msm_compute(const msm_bases *b, const void *d_scalars, void *d_result, void *d_work, void *stream);
+
 /* Measurement helper: the all-CU rate of the units the NTT's rooflines are
  * drawn on (the paper places its NTT kernels on the GPU's INT32 roofline,
  * Section IV-C).  One warm-up launch, then `reps` launches timed with HIP
@@ -325,6 +370,8 @@ int ntt_profile_passes(const ntt_plan *p, int kind, const void *d_in, void *d_ou
  *   ZK_MB_FFMUL_BLS12_381  Montgomery products/s over BLS12-381 Fr (three interleaved per thread,
  *                          four waves per SIMD, like the pass kernels); ZK_MB_FFMUL_K2 and
  *                          ZK_MB_FFMUL_K4 interleave two and four
+ *   ZK_MB_FFMUL_F64        Montgomery products/s over BLS12-381 Fr on the FP64 multiplier
+ *                          (three per thread, four waves per SIMD)
  *   ZK_MB_MAD_FMA          instructions/s of v_mad_u64_u32 and v_fma_f64 interleaved (independent)
  *   ZK_MB_MAD_ADD          instructions/s of v_mad_u64_u32 and v_add_u32 interleaved (independent)
  *   ZK_MB_COPY             bytes/s read plus written by a streaming copy of the
@@ -345,10 +392,19 @@ typedef enum {
   ZK_MB_FFMUL_K2 = 7,
   ZK_MB_FFMUL_K4 = 8,
   ZK_MB_MAD_FMA = 9,
-  ZK_MB_MAD_ADD = 10
+  ZK_MB_MAD_ADD = 10,
+  ZK_MB_FFMUL_F64 = 11
 } zk_microbench_kind;
 int zk_microbench(int kind, uint32_t iters, void *d_buf, size_t buf_bytes, void *stream, int reps,
                   double *ops_per_s, float *ms_per_launch);
+
+/* Element-wise Montgomery product, for checking the multipliers on their
+ * own: out_i = a_i b_i 2^-256 mod p with variant 0 (the integer FIPS product
+ * of every transform), a_i b_i 2^-288 mod p with variant 1 (the FP64
+ * product of ZK_FLAG_FFMUL_FP64 plans, whose radix is 2^288).  Inputs
+ * canonical, 256-byte aligned device arrays of n elements; asynchronous on
+ * `stream`.  out may equal a or b. */
+int zk_field_mul(int field, int variant, const void *d_a, const void *d_b, void *d_out, uint64_t n, void *stream);
 
 /* Thread-local description of the calling thread's last failure. */
 const char *zk_last_error(void);

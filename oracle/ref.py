@@ -229,3 +229,12 @@ def transform_mont(F: Field, kind: str, ys):
 
 def quotient_mont(F: Field, As, Bs, Cs):
     return F.to_mont(quotient(F, F.from_mont(As), F.from_mont(Bs), F.from_mont(Cs)))
+
+
+def montgomery_product(F: Field, xs, ys, radix_bits: int = R_BITS):
+    """Montgomery product with radix 2^radix_bits, by its definition:
+    x y 2^-radix_bits mod p for each pair (the FF_mul of the paper's
+    finite-field layer, Section IV-B, in Montgomery form).  With radix 2^256
+    it multiplies two stored elements; the FP64 multiplier uses 2^288."""
+    k = pow(2, -radix_bits, F.p)
+    return [x * y % F.p * k % F.p for x, y in zip(xs, ys)]

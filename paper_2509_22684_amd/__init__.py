@@ -10,6 +10,7 @@ binding raises.
 from ._lib import (  # noqa: F401
     FIELDS,
     Batch,
+    MsmBases,
     ntt_batch_create,
     ntt_batch_create_jobs,
     ntt_batch_destroy,
@@ -21,6 +22,8 @@ from ._lib import (  # noqa: F401
     ntt_batch_workspace_bytes,
     Plan,
     ZkError,
+    ZK_FLAG_FFMUL_FP64,
+    ZK_FLAG_VALIDATE,
     lib,
     ntt_coset_forward,
     ntt_coset_inverse,
@@ -44,6 +47,7 @@ from ._lib import (  # noqa: F401
     quotient_workspace_bytes,
     zk_copy_to_host,
     zk_microbench,
+    zk_field_mul,
     ntt_forward_noalloc,
     zk_last_error,
 )

@@ -17,6 +17,7 @@ FIELDS = {"bls12_381_fr": 1, "bn254_fr": 2, "bls12_377_fr": 3}
 FIELD_ADICITY = {"bls12_381_fr": 32, "bn254_fr": 28, "bls12_377_fr": 47}
 
 ZK_FLAG_VALIDATE = 1
+ZK_FLAG_FFMUL_FP64 = 2
 
 
 class ZkError(RuntimeError):
@@ -109,6 +110,21 @@ def lib() -> ctypes.CDLL:
         L.zk_microbench.argtypes = [ctypes.c_int, ctypes.c_uint32, vp, sz, vp, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]
         L.zk_microbench.restype = ctypes.c_int
+        L.zk_field_mul.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_uint64, vp]
+        L.zk_field_mul.restype = ctypes.c_int
+        L.msm_bases_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_uint64, ctypes.c_uint32, vp]
+        L.msm_bases_create.restype = ctypes.c_int
+        L.msm_bases_destroy.argtypes = [vp]
+        L.msm_bases_destroy.restype = None
+        L.msm_bases_count.argtypes = [vp]
+        L.msm_bases_count.restype = ctypes.c_uint64
+        L.msm_bases_window_bits.argtypes = [vp]
+        L.msm_bases_window_bits.restype = ctypes.c_int
+        for name in ("msm_bases_device_bytes", "msm_workspace_bytes"):
+            getattr(L, name).argtypes = [vp]
+            getattr(L, name).restype = sz
+        L.msm_compute.argtypes = [vp, vp, vp, vp, vp]
+        L.msm_compute.restype = ctypes.c_int
         L.zk_last_error.argtypes = []
         L.zk_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -317,8 +333,17 @@ def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -
     return [buf[k] for k in range(rc)]
 
 
+def zk_field_mul(field, variant: int, d_a, d_b, d_out, n: int | None = None, stream=None) -> None:
+    """out = a b 2^-256 (variant 0, integer) or a b 2^-288 (variant 1, FP64) mod p, element-wise."""
+    if n is None:
+        n = d_a.shape[0]
+    _check(lib().zk_field_mul(_field_id(field), variant, _ptr(d_a), _ptr(d_b), _ptr(d_out), n,
+                              _stream(stream, d_a)), "zk_field_mul")
+
+
 MICROBENCH = {"mad_u64_u32": 0, "fma_f64": 1, "add_u32": 2, "addc_u32": 3, "mad_addc": 4,
-              "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8, "mad_fma": 9, "mad_add": 10}
+              "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8, "mad_fma": 9, "mad_add": 10,
+              "ffmul_f64": 11}
 
 
 def zk_microbench(kind: str, d_buf, iters: int = 256, reps: int = 5, stream=None, buf_bytes: int | None = None):
@@ -557,6 +582,60 @@ class Batch:
     def close(self) -> None:
         if self.handle:
             ntt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Multi-scalar multiplication (BLS12-381 G1)
+
+class MsmBases:
+    """Fixed MSM bases: `points` is a device int32 tensor [n, 24] (affine x, y
+    as Montgomery limbs over F_q); the per-window multiples are precomputed
+    here, once."""
+
+    def __init__(self, points, window_bits: int = 0, stream=None):
+        import torch
+
+        self.n = points.shape[0]
+        h = ctypes.c_void_p()
+        _check(lib().msm_bases_create(ctypes.byref(h), _ptr(points), self.n, window_bits, _stream(stream, points)),
+               "msm_bases_create")
+        self.handle = h.value
+        self.device = points.device
+        self.window_bits = lib().msm_bases_window_bits(self.handle)
+        self._work = None
+        self.torch = torch
+
+    @property
+    def device_bytes(self) -> int:
+        return lib().msm_bases_device_bytes(self.handle)
+
+    def workspace(self):
+        if self._work is None:
+            nb = lib().msm_workspace_bytes(self.handle)
+            self._work = self.torch.empty((nb + 31) // 32, 8, dtype=self.torch.int32, device=self.device)
+        return self._work
+
+    def msm(self, scalars, out=None, work=None, stream=None):
+        """XYZZ result [48] int32 of sum s_i P_i; scalars [n, 8] Montgomery Fr."""
+        if scalars.shape[0] != self.n:
+            raise ValueError("one scalar per base point")
+        if out is None:
+            out = self.torch.empty(64, dtype=self.torch.int32, device=self.device)
+        _check(lib().msm_compute(self.handle, _ptr(scalars), _ptr(out), _ptr(work if work is not None else
+                                                                             self.workspace()),
+                                 _stream(stream, scalars)), "msm_compute")
+        return out
+
+    def close(self) -> None:
+        if self.handle:
+            lib().msm_bases_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

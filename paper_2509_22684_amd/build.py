@@ -21,7 +21,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "ntt_kernels.hip", "ntt_batch.hip", "microbench.hip",
            "ntt_pass_bls_e3.hip", "ntt_pass_bls_e2.hip", "ntt_pass_bls_e1.hip",
            "ntt_pass_bn_e3.hip", "ntt_pass_bn_e2.hip", "ntt_pass_bn_e1.hip",
-           "ntt_pass_b377_e3.hip", "ntt_pass_b377_e2.hip", "ntt_pass_b377_e1.hip"]
+           "ntt_pass_b377_e3.hip", "ntt_pass_b377_e2.hip", "ntt_pass_b377_e1.hip",
+           "ntt_pass_bls_f64_e2.hip", "msm.hip"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -32,6 +32,7 @@
 
 #include "../../include/zkntt.h"
 #include "field.hpp"
+#include "msm.hpp"
 #include "ntt_batch.hpp"
 #include "ntt_kernels.hpp"
 
@@ -77,7 +78,10 @@ struct ntt_plan {
   std::vector<void*> owned;  // device allocations
   size_t device_bytes = 0;
   Fe n_inv{};        // 1/n, Montgomery
+  Fe n_inv_op{};     // 1/n as the second operand of the plan's multiplier
   Fe zinv{};         // 1/(g^n - 1), Montgomery
+  int kfield = 0;    // field id the pass kernels are launched for
+  bool fp64 = false; // products on the FP64 multiplier (tables held as y 2^288)
   uint32_t twiddle_mode = 1;      // 1 table per pass, 2 two-level
   uint32_t max_log_r = 8;         // stages per global pass
   uint32_t log_tile = 10;         // elements per workgroup tile of a multi-pass transform, log2
@@ -204,6 +208,16 @@ int build_plan(ntt_plan* p) {
   const Fe g = zk::to_mont<F>(zk::fe_from_u32<F>(F::GENERATOR));
   const Fe g_inv = zk::inv_mont<F>(g);
   p->n_inv = zk::inv_mont<F>(zk::pow_mont_u64<F>(zk::add<F>(one, one), L));
+  // Second operands of the pass kernels' products (every table entry, 1/n):
+  // y 2^256 mod p for the integer multiplier, y 2^288 mod p for the FP64 one
+  // (R = 2^288 there), i.e. scaled by 2^32 in the Montgomery form.
+  Fe opscale = one;
+  if (p->fp64) {
+    Fe two32 = zk::fe_zero();
+    two32.v[1] = 1;
+    opscale = zk::to_mont<F>(two32);
+  }
+  p->n_inv_op = zk::mul_portable<F>(p->n_inv, opscale);
   {
     Fe gn = g;
     for (uint32_t i = 0; i < L; ++i) gn = zk::mul_portable<F>(gn, gn);  // g^n
@@ -227,7 +241,7 @@ int build_plan(ntt_plan* p) {
       if (int rc = tb.alloc(&t, R)) return rc;
       Fe w_r = w_n;  // w_R = w_n^(n/R)
       for (uint32_t i = 0; i < L - (uint32_t)d.log_r; ++i) w_r = zk::mul_portable<F>(w_r, w_r);
-      if (int rc = tb.generate<F>(t, R, w_r, one, zk::kGenPowers, 1, 0)) return rc;
+      if (int rc = tb.generate<F>(t, R, w_r, opscale, zk::kGenPowers, 1, 0)) return rc;
       tw_r_by_log[d.log_r] = t;
     }
     d.tw_r = tw_r_by_log[d.log_r];
@@ -236,7 +250,7 @@ int build_plan(ntt_plan* p) {
       const uint64_t count = ns * R;
       if (int rc = tb.alloc(&d.tw_pass, count)) return rc;
       // entry r * Ns + j' = w_n^((n / (Ns R)) r j')
-      if (int rc = tb.generate<F>(d.tw_pass, count, w_n, one, zk::kGenPassTwiddle, ns, p->n >> (log_ns + d.log_r)))
+      if (int rc = tb.generate<F>(d.tw_pass, count, w_n, opscale, zk::kGenPassTwiddle, ns, p->n >> (log_ns + d.log_r)))
         return rc;
     }
     p->passes.push_back(d);
@@ -248,20 +262,20 @@ int build_plan(ntt_plan* p) {
     p->log_lo = (L + 1) / 2;
     const uint64_t nlo = 1ull << p->log_lo, nhi = 1ull << (L - p->log_lo);
     if (int rc = tb.alloc(&p->tw_lo, nlo)) return rc;
-    if (int rc = tb.generate<F>(p->tw_lo, nlo, w_n, one, zk::kGenPowers, 1, 0)) return rc;
+    if (int rc = tb.generate<F>(p->tw_lo, nlo, w_n, opscale, zk::kGenPowers, 1, 0)) return rc;
     Fe w_step = w_n;
     for (uint32_t i = 0; i < p->log_lo; ++i) w_step = zk::mul_portable<F>(w_step, w_step);
     if (int rc = tb.alloc(&p->tw_hi, nhi)) return rc;
-    if (int rc = tb.generate<F>(p->tw_hi, nhi, w_step, one, zk::kGenPowers, 1, 0)) return rc;
+    if (int rc = tb.generate<F>(p->tw_hi, nhi, w_step, opscale, zk::kGenPowers, 1, 0)) return rc;
   }
 
   // Coset tables.
   if (int rc = tb.alloc(&p->coset_fwd, p->n)) return rc;
-  if (int rc = tb.generate<F>(p->coset_fwd, p->n, g, one, zk::kGenPowers, 1, 0)) return rc;
+  if (int rc = tb.generate<F>(p->coset_fwd, p->n, g, opscale, zk::kGenPowers, 1, 0)) return rc;
   if (int rc = tb.alloc(&p->coset_inv, p->n)) return rc;
-  if (int rc = tb.generate<F>(p->coset_inv, p->n, g_inv, p->n_inv, zk::kGenPowers, 1, 0)) return rc;
+  if (int rc = tb.generate<F>(p->coset_inv, p->n, g_inv, p->n_inv_op, zk::kGenPowers, 1, 0)) return rc;
   if (int rc = tb.alloc(&p->inv_to_coset, p->n)) return rc;
-  if (int rc = tb.generate<F>(p->inv_to_coset, p->n, g, p->n_inv, zk::kGenPowers, 1, 0)) return rc;
+  if (int rc = tb.generate<F>(p->inv_to_coset, p->n, g, p->n_inv_op, zk::kGenPowers, 1, 0)) return rc;
 
   {
     void* d = nullptr;
@@ -301,7 +315,7 @@ int check_opts(const ntt_plan_opts& o) {
   if (o.log2_radix > 3) return fail(ZK_EUNSUPPORTED, "log2_radix must be 0, 1, 2 or 3");
   if (!(o.log2_tile == 0 || o.log2_tile == 8 || o.log2_tile == 10 || o.log2_tile == 11))
     return fail(ZK_EUNSUPPORTED, "log2_tile must be 0, 8, 10 or 11");
-  if (o.flags & ~ZK_FLAG_VALIDATE) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
+  if (o.flags & ~(ZK_FLAG_VALIDATE | ZK_FLAG_FFMUL_FP64)) return fail(ZK_EUNSUPPORTED, "unknown flag bits");
   return ZK_OK;
 }
 
@@ -316,6 +330,14 @@ int resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* in, ntt_plan_op
   ntt_plan_opts o{};
   if (in) o = *in;
   if (int rc = check_opts(o)) return rc;
+  if (o.flags & ZK_FLAG_FFMUL_FP64) {
+    // the FP64 multiplier is built for BLS12-381 Fr with radix-4 rounds
+    if (field != ZK_FIELD_BLS12_381_FR)
+      return fail(ZK_EUNSUPPORTED, "ZK_FLAG_FFMUL_FP64 is available for BLS12-381 Fr only");
+    if (o.log2_radix && o.log2_radix != 2)
+      return fail(ZK_EUNSUPPORTED, "ZK_FLAG_FFMUL_FP64 runs radix-4 register rounds (log2_radix 0 or 2)");
+    o.log2_radix = 2;
+  }
   {
     TuningRegistry& reg = tuning_registry();
     std::lock_guard<std::mutex> lock(reg.mu);
@@ -418,7 +440,7 @@ zk::PassArgs make_pass_args(const ntt_plan* p, Kind kind, size_t k, const void* 
   if (k + 1 == P) {
     if (kind == kInverse) {
       a.flags |= zk::kPassPostConst;
-      a.post_const = p->n_inv;
+      a.post_const = p->n_inv_op;
     } else if (kind == kCosetInverse) {
       a.flags |= zk::kPassPostTable;
       a.post_table = p->coset_inv;
@@ -442,7 +464,7 @@ int run_transform(const ntt_plan* p, Kind kind, const void* in, void* out, void*
     }
     const PassDesc& d = p->passes[k];
     const zk::PassArgs a = make_pass_args(p, kind, k, in, out, work);
-    hipError_t e = zk::launch_pass(p->field, d.log_r, d.log_tile, p->log_e, a, s);
+    hipError_t e = zk::launch_pass(p->kfield, d.log_r, d.log_tile, p->log_e, a, s);
     if (e != hipSuccess) return hip_fail(e, "NTT pass launch");
   }
   if (events) {
@@ -553,6 +575,8 @@ int ntt_plan_create(ntt_plan** out, int field, uint32_t log2n, const ntt_plan_op
   p->max_log_r = o.log2_pass_radix;
   p->log_tile = o.log2_tile;
   p->opts = o;
+  p->fp64 = (o.flags & ZK_FLAG_FFMUL_FP64) != 0;
+  p->kfield = p->fp64 ? zk::kFieldBls12_381Fp64 : field;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     free_plan(p);
@@ -681,6 +705,7 @@ size_t quotient_workspace_bytes(const ntt_plan* p) {
 int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_H, void* d_work,
                   void* stream) {
   if (!p) return fail(ZK_EINVAL, "null plan");
+  if (p->fp64) return fail(ZK_EUNSUPPORTED, "the quotient chain runs on the integer multiplier only");
   if (!d_A || !d_B || !d_C || !d_H || !d_work) return fail(ZK_EINVAL, "null pointer");
   if (!aligned(d_A) || !aligned(d_B) || !aligned(d_C) || !aligned(d_H) || !aligned(d_work))
     return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
@@ -753,6 +778,7 @@ int quotient_poly(const ntt_plan* p, const void* d_A, const void* d_B, const voi
 }
 
 int quotient_coset_evals(const ntt_plan* p, const void* d_in, void* d_out, void* d_work, void* stream) {
+  if (p && p->fp64) return fail(ZK_EUNSUPPORTED, "the quotient chain runs on the integer multiplier only");
   if (int rc = transform_entry(p, kInverseRaw, d_in, d_out, d_work, stream)) return rc;
   return run_transform(p, kForwardShifted, d_out, d_out, d_work, static_cast<hipStream_t>(stream));
 }
@@ -760,6 +786,7 @@ int quotient_coset_evals(const ntt_plan* p, const void* d_in, void* d_out, void*
 int quotient_pointwise(const ntt_plan* p, const void* d_A, const void* d_B, const void* d_C, void* d_out,
                        void* stream) {
   if (!p) return fail(ZK_EINVAL, "null plan");
+  if (p->fp64) return fail(ZK_EUNSUPPORTED, "the quotient chain runs on the integer multiplier only");
   if (!d_A || !d_B || !d_C || !d_out) return fail(ZK_EINVAL, "null pointer");
   if (!aligned(d_A) || !aligned(d_B) || !aligned(d_C) || !aligned(d_out))
     return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
@@ -825,6 +852,17 @@ int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_ou
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   return rc ? rc : P;
+}
+
+int zk_field_mul(int field, int variant, const void* d_a, const void* d_b, void* d_out, uint64_t n, void* stream) {
+  if (!field_adicity(field)) return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
+  if (variant != 0 && variant != 1) return fail(ZK_EUNSUPPORTED, "variant must be 0 (integer) or 1 (FP64)");
+  if (n && (!d_a || !d_b || !d_out)) return fail(ZK_EINVAL, "null pointer");
+  if ((n && (!aligned(d_a) || !aligned(d_b) || !aligned(d_out))))
+    return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
+  hipError_t e = zk::launch_field_mul(field, variant, static_cast<const Fe*>(d_a), static_cast<const Fe*>(d_b),
+                                      static_cast<Fe*>(d_out), n, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "field multiplication launch");
 }
 
 const char* zk_last_error(void) { return g_last_error.c_str(); }
@@ -937,6 +975,19 @@ void give_back(int dev, const std::vector<hipStream_t>& streams, const std::vect
     if (x) sp.streams.emplace_back(dev, x);
   for (hipEvent_t x : events)
     if (x) sp.events.emplace_back(dev, x);
+}
+
+// A synchronous copy on a pooled non-blocking stream: ordered after nothing
+// but itself, so it never waits for work the caller has queued elsewhere.
+hipError_t copy_on_own_stream(int dev, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  if (bytes == 0) return hipSuccess;
+  hipStream_t xs = nullptr;
+  hipError_t e = take_stream(dev, &xs);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(dst, src, bytes, kind, xs);
+  if (e == hipSuccess) e = hipStreamSynchronize(xs);
+  give_back(dev, {xs}, {});
+  return e;
 }
 
 // Device memory for batch descriptors is recycled the same way: hipFree
@@ -1082,6 +1133,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     const ntt_batch_job& sp = specs[k];
     const ntt_plan* p = sp.plan;
     if (!p) return fail(ZK_EINVAL, "null plan in batch job " + std::to_string(k));
+    if (p->fp64) return fail(ZK_EUNSUPPORTED, "batches run on the integer multiplier only");
     if (p->device != dev) return fail(ZK_EINVAL, "batch plans must live on the current device");
     zk::BatchJob& J = jobs[k];
     std::memset(&J, 0, sizeof J);
@@ -1370,19 +1422,27 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       d.pass[q].grp_in = reinterpret_cast<const Fe* const*>(d_ptrs + d.ptr_off[q]);
       d.pass[q].grp_out = reinterpret_cast<Fe* const*>(d_ptrs + d.ptr_off[q] + d.pass[q].grp_jobs);
     }
-  std::vector<uint32_t> ctl(ctl_words, 0);
-  ctl[zk::kCtlSpinLimit] = kDefaultSpinLimit;
-  if (!jobs.empty()) e = hipMemcpy(b->d_jobs, jobs.data(), sizeof(zk::BatchJob) * jobs.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !items.empty())
-    e = hipMemcpy(b->d_items, items.data(), sizeof(zk::BatchItem) * items.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !queues.empty())
-    e = hipMemcpy(b->d_queues, queues.data(), sizeof(zk::BatchQueue) * queues.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_ctl, ctl.data(), ctl_words * sizeof(uint32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !ptrs.empty())
-    e = hipMemcpy(d_ptrs, ptrs.data(), ptrs.size() * sizeof(uintptr_t), hipMemcpyHostToDevice);
+  // All descriptors in one host image of the block, uploaded with one copy
+  // on a stream of the library's own (a copy on the null stream could be
+  // ordered after work the caller has queued on other streams).
+  const size_t used = jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t);
+  std::vector<char> image(used, 0);
+  if (!jobs.empty()) std::memcpy(image.data(), jobs.data(), sizeof(zk::BatchJob) * jobs.size());
+  if (!items.empty()) std::memcpy(image.data() + jobs_bytes, items.data(), sizeof(zk::BatchItem) * items.size());
+  if (!queues.empty())
+    std::memcpy(image.data() + jobs_bytes + items_bytes, queues.data(), sizeof(zk::BatchQueue) * queues.size());
+  {
+    std::vector<uint32_t> ctl(ctl_words, 0);
+    ctl[zk::kCtlSpinLimit] = kDefaultSpinLimit;
+    std::memcpy(image.data() + jobs_bytes + items_bytes + queues_bytes, ctl.data(), ctl_words * sizeof(uint32_t));
+  }
+  if (!ptrs.empty())
+    std::memcpy(image.data() + jobs_bytes + items_bytes + queues_bytes + ctl_bytes, ptrs.data(),
+                ptrs.size() * sizeof(uintptr_t));
+  e = copy_on_own_stream(dev, b->d_mem, image.data(), used, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_batch(b);
-    return hip_fail(e, "hipMemcpy(batch descriptors)");
+    return hip_fail(e, "batch descriptor upload");
   }
   if (capture) {
     // One graph: the direct jobs' passes, the counter reset kernel and the
@@ -1478,7 +1538,7 @@ int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
 int ntt_batch_status(const ntt_batch* b) {
   if (!b) return fail(ZK_EINVAL, "null batch");
   uint32_t err = 0;
-  hipError_t e = hipMemcpy(&err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
+  hipError_t e = copy_on_own_stream(b->device, &err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "batch status readback");
   if (err & zk::kBatchErrWait)
     return fail(ZK_EDEVICE, "a batched dependency wait exceeded its poll limit; outputs are invalid");
@@ -1488,7 +1548,8 @@ int ntt_batch_status(const ntt_batch* b) {
 
 int ntt_batch_set_spin_limit(ntt_batch* b, uint32_t polls) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  hipError_t e = hipMemcpy(b->d_ctl + zk::kCtlSpinLimit, &polls, sizeof polls, hipMemcpyHostToDevice);
+  hipError_t e = copy_on_own_stream(b->device, b->d_ctl + zk::kCtlSpinLimit, &polls, sizeof polls,
+                                    hipMemcpyHostToDevice);
   return e == hipSuccess ? ZK_OK : hip_fail(e, "batch spin limit");
 }
 
@@ -1511,6 +1572,165 @@ int ntt_batch_forward(const ntt_plan* const* plans, void* const* d_bufs, int njo
   }
   free_batch(b);
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Multi-scalar multiplication (BLS12-381 G1)
+
+struct msm_bases {
+  int device = 0;
+  uint64_t n = 0;
+  int c = 0;
+  int windows = 0;
+  uint32_t slices = 1;
+  uint32_t chunk = 16;
+  void* table = nullptr;
+};
+
+namespace {
+
+constexpr int kScalarBits = 255;  // BLS12-381 Fr elements are below 2^255
+
+struct MsmLayout {
+  size_t digits, counts, offsets, cursors, entries, partial, buckets, level_a, level_b, total;
+};
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+MsmLayout msm_layout(const msm_bases* b) {
+  MsmLayout L{};
+  const size_t nb = size_t(1) << b->c;
+  const size_t entries = (size_t)b->windows * b->n;
+  const size_t T = (nb + b->chunk - 1) / b->chunk;
+  const size_t xyzz = zk::msm::kXyzzWords * sizeof(uint32_t);
+  size_t off = 0;
+  L.digits = off;
+  off += round256(entries * sizeof(uint16_t));
+  L.counts = off;
+  off += round256(nb * sizeof(uint32_t));
+  L.offsets = off;
+  off += round256((nb + 1) * sizeof(uint32_t));
+  L.cursors = off;
+  off += round256(nb * sizeof(uint32_t));
+  L.entries = off;
+  off += round256(entries * sizeof(uint32_t));
+  L.partial = off;
+  off += round256(nb * b->slices * xyzz);
+  L.buckets = off;
+  off += round256(nb * xyzz);
+  L.level_a = off;
+  off += round256((size_t)b->c * T * xyzz);
+  L.level_b = off;
+  off += round256((size_t)b->c * T * xyzz);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msm_bases_create(msm_bases** out, const void* d_points, uint64_t n, uint32_t window_bits, void* stream) {
+  if (!out) return fail(ZK_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (n == 0) return fail(ZK_EINVAL, "an MSM needs at least one point");
+  if (!d_points || !aligned(d_points)) return fail(ZK_EINVAL, "points must be non-null and 256-byte aligned");
+  if (window_bits > 16) return fail(ZK_EUNSUPPORTED, "window_bits must be 0 (automatic) or 1..16");
+  int c = (int)window_bits;
+  if (!c) {
+    int lg = 0;
+    while ((1ull << (lg + 1)) <= n) ++lg;
+    c = std::max(4, std::min(16, lg - 2));
+  }
+  const int windows = (kScalarBits + c - 1) / c;
+  if ((uint64_t)windows * n >= (1ull << 32)) return fail(ZK_EUNSUPPORTED, "too many points for this window size");
+  msm_bases* b = new (std::nothrow) msm_bases();
+  if (!b) return fail(ZK_ENOMEM, "host allocation failed");
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipGetDevice");
+  }
+  b->n = n;
+  b->c = c;
+  b->windows = windows;
+  b->slices = std::max<uint32_t>(1, (1u << 18) >> c);
+  const size_t table_bytes = (size_t)windows * n * zk::msm::kPointWords * sizeof(uint32_t);
+  e = hipMalloc(&b->table, table_bytes);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipMalloc(MSM table)");
+  }
+  // the precomputation's XYZZ scratch, a chunk of points at a time
+  const uint64_t chunk_pts = std::min<uint64_t>(n, 1ull << 18);
+  void* scratch = nullptr;
+  e = hipMalloc(&scratch, (size_t)chunk_pts * windows * 60 * sizeof(uint32_t));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t* pts = static_cast<const uint32_t*>(d_points);
+  uint32_t* table = static_cast<uint32_t*>(b->table);
+  for (uint64_t lo = 0; lo < n && e == hipSuccess; lo += chunk_pts)
+    e = zk::msm::launch_precompute(pts, n, lo, std::min<uint64_t>(chunk_pts, n - lo), c, windows, table,
+                                   static_cast<uint32_t*>(scratch), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (scratch) (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    (void)hipFree(b->table);
+    delete b;
+    return hip_fail(e, "MSM precomputation");
+  }
+  *out = b;
+  return ZK_OK;
+}
+
+void msm_bases_destroy(msm_bases* b) {
+  if (!b) return;
+  if (b->table) (void)hipFree(b->table);
+  delete b;
+}
+
+uint64_t msm_bases_count(const msm_bases* b) { return b ? b->n : 0; }
+
+int msm_bases_window_bits(const msm_bases* b) { return b ? b->c : 0; }
+
+size_t msm_bases_device_bytes(const msm_bases* b) {
+  return b ? (size_t)b->windows * b->n * zk::msm::kPointWords * sizeof(uint32_t) : 0;
+}
+
+size_t msm_workspace_bytes(const msm_bases* b) { return b ? msm_layout(b).total : 0; }
+
+int msm_compute(const msm_bases* b, const void* d_scalars, void* d_result, void* d_work, void* stream) {
+  if (!b) return fail(ZK_EINVAL, "null bases");
+  if (!d_scalars || !d_result || !d_work) return fail(ZK_EINVAL, "null pointer");
+  if (!aligned(d_scalars) || !aligned(d_result) || !aligned(d_work))
+    return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != b->device) return fail(ZK_EINVAL, "the current HIP device is not the bases' device");
+  const MsmLayout L = msm_layout(b);
+  char* w = static_cast<char*>(d_work);
+  zk::msm::MsmLaunch m{};
+  m.table = static_cast<const uint32_t*>(b->table);
+  m.scalars = static_cast<const uint32_t*>(d_scalars);
+  m.n = b->n;
+  m.c = b->c;
+  m.windows = b->windows;
+  m.slices = b->slices;
+  m.chunk = b->chunk;
+  m.digits = reinterpret_cast<uint16_t*>(w + L.digits);
+  m.counts = reinterpret_cast<uint32_t*>(w + L.counts);
+  m.offsets = reinterpret_cast<uint32_t*>(w + L.offsets);
+  m.cursors = reinterpret_cast<uint32_t*>(w + L.cursors);
+  m.entries = reinterpret_cast<uint32_t*>(w + L.entries);
+  m.partial = reinterpret_cast<uint32_t*>(w + L.partial);
+  m.buckets = reinterpret_cast<uint32_t*>(w + L.buckets);
+  m.level_a = reinterpret_cast<uint32_t*>(w + L.level_a);
+  m.level_b = reinterpret_cast<uint32_t*>(w + L.level_b);
+  m.result = static_cast<uint32_t*>(d_result);
+  e = zk::msm::launch_msm(m, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ZK_OK : hip_fail(e, "MSM launch");
 }
 
 }  // extern "C"

@@ -26,10 +26,19 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace zk {
 
 constexpr int kLimbs = 8;
+
+// A field type may bring its own Montgomery multiplier (F::kAltMul = true,
+// F::mul(a, b)): mul and mul_k below then call it instead of the integer
+// FIPS product (field_f64.hpp uses this for the FP64 variant).
+template <class F, class = void>
+struct HasAltMul : std::false_type {};
+template <class F>
+struct HasAltMul<F, std::void_t<decltype(F::kAltMul)>> : std::bool_constant<F::kAltMul> {};
 
 // BLS12-381 scalar field Fr.  2-adicity 32; 7 generates the multiplicative group.
 struct Bls12_381Fr {
@@ -202,6 +211,7 @@ __device__ __forceinline__ uint32_t add_carry(uint32_t x, uint64_t ci) {
 
 template <class F>
 __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
+  if constexpr (HasAltMul<F>::value) return F::mul(a, b);
   uint32_t m[kLimbs], r[kLimbs];
   uint64_t acc = 0;  // current column, low 64 bits
   uint32_t hi = 0;   // overflow count of the current column
@@ -258,6 +268,11 @@ __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
 // identical to mul().
 template <class F, int K>
 __device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
+  if constexpr (HasAltMul<F>::value) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = F::mul(a[k], b[k]);
+    return;
+  }
   uint32_t m[K][kLimbs], t[K][kLimbs];
   uint64_t acc[K], co[K];
   uint32_t hi[K];

@@ -1,0 +1,201 @@
+// The base field of BLS12-381 G1, F_q (381-bit q), for the MSM kernels.
+//
+// An element is twelve 32-bit limbs, little-endian, in Montgomery form with
+// R = 2^384, canonical in [0, q).  FF_mul is the same finely integrated
+// product scanning as the scalar fields' (field.hpp): each 32x32-bit
+// partial product is one v_mad_u64_u32 into a 64-bit column accumulator
+// whose carry-out feeds a v_addc_co_u32 column counter, 2 N^2 = 288 of each
+// per product; K independent products interleave column by column, each
+// chain keeping its own carry SGPR pair.  FF_add / FF_sub are branchless
+// carry chains with a borrow-select.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace zk {
+namespace fq {
+
+constexpr int kN = 12;
+
+// q = (x0 - 1)^2 (x0^4 - x0^2 + 1) / 3 + x0, x0 = -0xd201000000010000.
+constexpr uint32_t kQ[kN] = {0xffffaaabu, 0xb9feffffu, 0xb153ffffu, 0x1eabfffeu, 0xf6b0f624u, 0x6730d2a0u,
+                             0xf38512bfu, 0x64774b84u, 0x434bacd7u, 0x4b1ba7b6u, 0x397fe69au, 0x1a0111eau};
+constexpr uint32_t kInv = 0xfffcfffdu;  // -q^-1 mod 2^32
+// 2^384 mod q: the Montgomery form of 1.
+constexpr uint32_t kOne[kN] = {0x0002fffdu, 0x76090000u, 0xc40c0002u, 0xebf4000bu, 0x53c758bau, 0x5f489857u,
+                               0x70525745u, 0x77ce5853u, 0xa256ec6du, 0x5c071a97u, 0xfa80e493u, 0x15f65ec3u};
+
+struct __align__(16) Fq {
+  uint32_t v[kN];
+};
+
+__device__ __forceinline__ Fq zero() {
+  Fq r;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) r.v[j] = 0;
+  return r;
+}
+
+__device__ __forceinline__ Fq one() {
+  Fq r;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) r.v[j] = kOne[j];
+  return r;
+}
+
+__device__ __forceinline__ bool is_zero(const Fq& a) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) o |= a.v[j];
+  return o == 0;
+}
+
+__device__ __forceinline__ bool equal(const Fq& a, const Fq& b) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) o |= a.v[j] ^ b.v[j];
+  return o == 0;
+}
+
+// a + b mod q (a, b canonical; a + b < 2q < 2^384).
+__device__ __forceinline__ Fq add(const Fq& a, const Fq& b) {
+  Fq s, d;
+  unsigned int c = 0, br = 0;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) s.v[j] = __builtin_addc(a.v[j], b.v[j], c, &c);
+#pragma unroll
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(s.v[j], kQ[j], br, &br);
+#pragma unroll
+  for (int j = 0; j < kN; ++j) d.v[j] = br ? s.v[j] : d.v[j];
+  return d;
+}
+
+// a - b mod q.
+__device__ __forceinline__ Fq sub(const Fq& a, const Fq& b) {
+  Fq d;
+  unsigned int br = 0, c = 0;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(a.v[j], b.v[j], br, &br);
+  const uint32_t mask = 0u - br;
+#pragma unroll
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_addc(d.v[j], kQ[j] & mask, c, &c);
+  return d;
+}
+
+__device__ __forceinline__ Fq dbl(const Fq& a) { return add(a, a); }
+
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ uint64_t mad_vv(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "+s"(co) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint64_t mad_vs(uint32_t a, uint32_t b, uint64_t c, uint64_t& co) {
+  uint64_t r;
+  asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "+s"(co) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t addc(uint32_t x, uint64_t& co) {
+  uint32_t r;
+  asm volatile("v_addc_co_u32_e64 %0, %1, %2, 0, %1" : "=v"(r), "+s"(co) : "v"(x));
+  return r;
+}
+
+// K independent Montgomery products r[k] = a[k] b[k] 2^-384 mod q, column by
+// column in lock step (see the file comment).
+template <int K>
+__device__ __forceinline__ void mul_k(Fq* r, const Fq* a, const Fq* b) {
+  uint32_t m[K][kN], t[K][kN];
+  uint64_t acc[K], co[K];
+  uint32_t hi[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = 0;
+    hi[k] = 0;
+    co[k] = 0;
+  }
+#define ZK_FQ_TERMS(X, Y, MADFN)                                                  \
+  {                                                                               \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) acc[k] = MADFN(X, Y, acc[k], co[k]); \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) hi[k] = addc(hi[k], co[k]);     \
+  }
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      ZK_FQ_TERMS(a[k].v[j], b[k].v[i - j], mad_vv);
+      ZK_FQ_TERMS(m[k][j], kQ[i - j], mad_vs);
+    }
+    ZK_FQ_TERMS(a[k].v[i], b[k].v[0], mad_vv);
+#pragma unroll
+    for (int k = 0; k < K; ++k) m[k][i] = (uint32_t)acc[k] * kInv;
+    ZK_FQ_TERMS(m[k][i], kQ[0], mad_vs);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
+      hi[k] = 0;
+    }
+  }
+#pragma unroll
+  for (int i = kN; i < 2 * kN; ++i) {
+#pragma unroll
+    for (int j = i - (kN - 1); j < kN; ++j) {
+      ZK_FQ_TERMS(a[k].v[j], b[k].v[i - j], mad_vv);
+      ZK_FQ_TERMS(m[k][j], kQ[i - j], mad_vs);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      t[k][i - kN] = (uint32_t)acc[k];
+      acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
+      hi[k] = 0;
+    }
+  }
+#undef ZK_FQ_TERMS
+  // t < 2q: one conditional subtraction
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    Fq d;
+    unsigned int br = 0;
+#pragma unroll
+    for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(t[k][j], kQ[j], br, &br);
+#pragma unroll
+    for (int j = 0; j < kN; ++j) r[k].v[j] = br ? t[k][j] : d.v[j];
+  }
+}
+#else
+// Host compilation pass: device code is parsed but never emitted here.
+template <int K>
+__device__ inline void mul_k(Fq* r, const Fq* a, const Fq* b) {
+  for (int k = 0; k < K; ++k) r[k] = a[k];
+  (void)b;
+}
+#endif
+
+__device__ __forceinline__ Fq mul(const Fq& a, const Fq& b) {
+  Fq r;
+  mul_k<1>(&r, &a, &b);
+  return r;
+}
+__device__ __forceinline__ void mul2(Fq& r0, const Fq& a0, const Fq& b0, Fq& r1, const Fq& a1, const Fq& b1) {
+  Fq a[2] = {a0, a1}, b[2] = {b0, b1}, r[2];
+  mul_k<2>(r, a, b);
+  r0 = r[0];
+  r1 = r[1];
+}
+__device__ __forceinline__ Fq sqr(const Fq& a) { return mul(a, a); }
+
+// a^-1 = a^(q-2) (Fermat), left-to-right square-and-multiply; a != 0.
+__device__ __forceinline__ Fq inverse(const Fq& a) {
+  // q - 2 differs from q only in the lowest limb (q mod 2^32 >= 2)
+  Fq r = one();
+#pragma unroll 1
+  for (int i = 32 * kN - 1; i >= 0; --i) {
+    r = sqr(r);
+    const uint32_t e = (i < 32) ? kQ[0] - 2u : kQ[i / 32];
+    if ((e >> (i % 32)) & 1u) r = mul(r, a);
+  }
+  return r;
+}
+
+}  // namespace fq
+}  // namespace zk

@@ -18,6 +18,7 @@
 
 #include "../../include/zkntt.h"
 #include "field.hpp"
+#include "field_f64.hpp"
 
 namespace zk {
 namespace {
@@ -107,6 +108,30 @@ __global__ void __launch_bounds__(kThreads) ffmul_kernel(uint32_t iters, uint32_
   out[gid] = r;
 }
 
+// The same on the FP64 multiplier (three independent products per trip).
+__global__ void __launch_bounds__(kThreads) ffmul_f64_kernel(uint32_t iters, uint32_t seed,
+                                                             uint64_t* __restrict__ out) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  Fe x[3], y[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < kLimbs; ++j) {
+      x[k].v[j] = (j == kLimbs - 1) ? (seed + gid + (uint32_t)k) & 0x0fffffffu : seed * 2654435761u + gid * (j + 1);
+      y[k].v[j] = (j == kLimbs - 1) ? (gid * 7u + (uint32_t)k) & 0x0fffffffu : gid * 40503u + (uint32_t)(j * k);
+    }
+  for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[k] = mul_f64<Bls12_381Fr>(x[k], y[k]);
+  }
+  uint64_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < kLimbs; ++j) r = r * 31 + x[k].v[j];
+  out[gid] = r;
+}
+
 __global__ void __launch_bounds__(kThreads) copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
                                                         uint64_t nvec) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -127,7 +152,8 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return ZK_EDEVICE;
   // eight 256-thread workgroups per CU (32 waves, 8 per SIMD); the products
   // run at the pass kernels' occupancy, four waves per SIMD
-  const bool ffmul = kind == ZK_MB_FFMUL_BLS12_381 || kind == ZK_MB_FFMUL_K2 || kind == ZK_MB_FFMUL_K4;
+  const bool ffmul = kind == ZK_MB_FFMUL_BLS12_381 || kind == ZK_MB_FFMUL_K2 || kind == ZK_MB_FFMUL_K4 ||
+                     kind == ZK_MB_FFMUL_F64;
   const uint32_t blocks = (uint32_t)cus * (ffmul ? 4u : 8u);
   const uint64_t lanes = (uint64_t)blocks * kThreads;
   double ops = 0;  // per launch
@@ -164,6 +190,9 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       case ZK_MB_FFMUL_K4:
         hipLaunchKernelGGL((ffmul_kernel<Bls12_381Fr, 4>), dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
         break;
+      case ZK_MB_FFMUL_F64:
+        hipLaunchKernelGGL(ffmul_f64_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
+        break;
       case ZK_MB_COPY: {
         const uint64_t nvec = buf_bytes / 32;  // half the buffer read, half written
         hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(kThreads), 0, s,
@@ -189,6 +218,7 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       ops = (double)lanes * iters * kUnroll * kChains * 2;  // two instructions per step
       break;
     case ZK_MB_FFMUL_BLS12_381:
+    case ZK_MB_FFMUL_F64:
       ops = (double)lanes * iters * 3;
       break;
     case ZK_MB_FFMUL_K2:

@@ -4,6 +4,7 @@
 // parallel.
 #include <algorithm>
 
+#include "field_f64.hpp"
 #include "ntt_kernels.hpp"
 #include "ntt_pass_impl.hpp"
 
@@ -18,6 +19,7 @@ hipError_t launch_pass_bn_e1(int log_r, int log_tile, const PassArgs& a, hipStre
 hipError_t launch_pass_b377_e3(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_b377_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_b377_e1(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_bls_f64_e2(int log_r, int log_tile, const PassArgs& a, hipStream_t s);
 
 namespace {
 using detail::load_fe;
@@ -64,6 +66,15 @@ __global__ void __launch_bounds__(256) validate_kernel(const Fe* __restrict__ x,
   if (!br) atomicAdd(count, 1u);  // v >= p
 }
 
+template <class F, int VARIANT>
+__global__ void __launch_bounds__(256) field_mul_kernel(const Fe* __restrict__ a, const Fe* __restrict__ b,
+                                                         Fe* __restrict__ out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Fe x = load_fe(a, i), y = load_fe(b, i);
+  store_fe(out, i, VARIANT == 1 ? mul_f64<F>(x, y) : mul<F>(x, y));
+}
+
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 }  // namespace
@@ -81,8 +92,30 @@ hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const Pass
     if (log_e == 3) return launch_pass_b377_e3(log_r, log_tile, a, s);
     if (log_e == 2) return launch_pass_b377_e2(log_r, log_tile, a, s);
     if (log_e == 1) return launch_pass_b377_e1(log_r, log_tile, a, s);
+  } else if (field == kFieldBls12_381Fp64) {
+    if (log_e == 2) return launch_pass_bls_f64_e2(log_r, log_tile, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_field_mul(int field, int variant, const Fe* a, const Fe* b, Fe* out, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (variant != 0 && variant != 1) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for(n, 256)), block(256);
+#define ZK_FIELD_MUL(FT)                                                                          \
+  if (variant == 0) hipLaunchKernelGGL((field_mul_kernel<FT, 0>), grid, block, 0, s, a, b, out, n); \
+  else hipLaunchKernelGGL((field_mul_kernel<FT, 1>), grid, block, 0, s, a, b, out, n);
+  if (field == Bls12_381Fr::ID) {
+    ZK_FIELD_MUL(Bls12_381Fr)
+  } else if (field == Bn254Fr::ID) {
+    ZK_FIELD_MUL(Bn254Fr)
+  } else if (field == Bls12_377Fr::ID) {
+    ZK_FIELD_MUL(Bls12_377Fr)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef ZK_FIELD_MUL
+  return hipGetLastError();
 }
 
 hipError_t launch_gen(int field, const GenArgs& g, hipStream_t s) {

@@ -63,6 +63,14 @@ inline bool pass_shape_supported(int log_r, int log_tile, int log_e = 2) {
   return log_tile == log_r && log_r >= 0 && log_r <= 10;
 }
 
+// Kernel field id of BLS12-381 Fr with products on the FP64 multiplier
+// (field_f64.hpp); launch_pass takes it like a field id.
+constexpr int kFieldBls12_381Fp64 = 101;
+
+// out_i = a_i b_i 2^-256 mod p (variant 0, the integer FIPS product) or
+// a_i b_i 2^-288 mod p (variant 1, the FP64 product), for i < n.
+hipError_t launch_field_mul(int field, int variant, const Fe* a, const Fe* b, Fe* out, uint64_t n, hipStream_t s);
+
 // Launch one pass; log_r + log_j = log_tile.  Returns hipSuccess or the
 // launch error.
 hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const PassArgs& a, hipStream_t s);

@@ -450,3 +450,19 @@ def test_planted_quotient_mistake_is_caught():
     bad = [v * fix % F.p for v in good]
     assert good == quotient_closed_form(F, A, B, C)
     assert bad != quotient_closed_form(F, A, B, C)
+
+
+@pytest.mark.parametrize("F", FIELDS, ids=IDS)
+def test_montgomery_product_definition(F):
+    """The Montgomery product of stored elements is the stored form of the
+    plain product (to_mont(x) * to_mont(y) * 2^-256 = to_mont(x y)), and
+    with radix 2^288 a second operand held as y 2^288 gives the same."""
+    rng = random.Random(3)
+    xs = [rng.randrange(F.p) for _ in range(20)] + [0, 1, F.p - 1]
+    ys = [rng.randrange(F.p) for _ in range(20)] + [F.p - 1, 0, F.p - 1]
+    got = ref.montgomery_product(F, F.to_mont(xs), F.to_mont(ys))
+    assert got == F.to_mont([x * y % F.p for x, y in zip(xs, ys)])
+    y288 = [(y << 288) % F.p for y in ys]
+    assert ref.montgomery_product(F, F.to_mont(xs), y288, 288) == got
+    # a planted mistake (radix 2^255) breaks the identity
+    assert ref.montgomery_product(F, F.to_mont(xs), F.to_mont(ys), 255) != got
