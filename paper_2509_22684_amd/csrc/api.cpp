@@ -1238,7 +1238,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     const int log_tile = p->passes[0].log_tile;
     const uint64_t tiles = (p->n >> log_tile) * groups[g].size();  // per pass, at the plan's tile
     const double slots = (double)cus * (log_tile >= 11 ? 2 : 4);
-    const double round_us = kRoundUs * (double)(1u << (log_tile > 10 ? log_tile - 10 : 0));
+    const double round_us = kRoundUs * std::ldexp(1.0, log_tile - 10);  // a round's work scales with the tile
     grouped_us[g] = (double)p->passes.size() * (kLaunchUs + std::ceil((double)tiles / slots) * round_us);
     group_items[g] = (double)(load(groups[g][0]) * groups[g].size());
     alone_us[g] = (double)load(groups[g][0]) * kBatchItemUs / (batch_slots / zk::kXcds);
