@@ -358,9 +358,14 @@ int resolve_opts(int field, uint32_t log2n, const ntt_plan_opts* in, ntt_plan_op
   // third pass would cost another launch or, in a batch, another round of
   // tiles and dependency waits); above, passes of at most 2^8 points, which
   // measured fastest at 2^24.
+  // Tile: 2^8 elements for radix-2 transforms of 2^10 to 2^16 points (they
+  // do not fill the chip; smaller tiles spread a pass over four times the
+  // workgroups: 2^12 in 24 us against 33 us with 2^10-element tiles), 2^10
+  // otherwise (the pass split under 2^8 tiles, passes of at most 2^7 points,
+  // would add a pass to batched jobs).
   if (!o.twiddle_mode) o.twiddle_mode = 1;
   if (!o.log2_radix) o.log2_radix = log2n <= 18 ? 1 : 2;
-  if (!o.log2_tile) o.log2_tile = 10;
+  if (!o.log2_tile) o.log2_tile = (log2n >= 10 && log2n <= 16 && o.log2_radix == 1) ? 8 : 10;
   if (!o.log2_pass_radix) o.log2_pass_radix = log2n <= 18 ? 9 : 8;
   if (o.log2_tile == 8 && o.log2_radix == 3 && log2n > 8)
     return fail(ZK_EUNSUPPORTED, "2^8-element tiles take two or four elements per thread (log2_radix 1 or 2)");

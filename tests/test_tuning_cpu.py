@@ -23,7 +23,10 @@ def test_builtin_defaults_without_registration():
     assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 24) == dict(
         twiddle_mode=1, log2_radix=2, log2_tile=10, flags=0, log2_pass_radix=8)
     assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 16) == dict(
-        twiddle_mode=1, log2_radix=1, log2_tile=10, flags=0, log2_pass_radix=9)
+        twiddle_mode=1, log2_radix=1, log2_tile=8, flags=0, log2_pass_radix=9)
+    assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 9)["log2_tile"] == 10
+    assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 17)["log2_tile"] == 10
+    assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 12, log2_radix=3)["log2_tile"] == 10
 
 
 def test_default_plan_picks_up_the_database_schedule(tmp_path):
@@ -43,7 +46,7 @@ def test_default_plan_picks_up_the_database_schedule(tmp_path):
         twiddle_mode=2, log2_radix=3, log2_tile=11, flags=0, log2_pass_radix=7)
     # fields the database leaves open keep the built-in defaults
     assert _lib.ntt_plan_resolve_opts("bls12_381_fr", 12) == dict(
-        twiddle_mode=1, log2_radix=3, log2_tile=10, flags=0, log2_pass_radix=9)
+        twiddle_mode=1, log2_radix=3, log2_tile=10, flags=0, log2_pass_radix=9)  # radix 8 keeps 2^10 tiles
     # explicit options win over the database
     assert _lib.ntt_plan_resolve_opts("bn254_fr", 20, log2_radix=1, flags=1)["log2_radix"] == 1
     assert _lib.ntt_plan_resolve_opts("bn254_fr", 20, log2_radix=1, flags=1)["flags"] == 1
@@ -92,7 +95,7 @@ def test_plan_table_bytes_on_the_host():
     n = 1 << 24
     assert _lib.ntt_plan_table_bytes("bls12_381_fr", 24) == 32 * (256 + (1 << 16) + n + 3 * n)
     assert _lib.ntt_plan_table_bytes("bls12_381_fr", 33) == 0
-    assert _lib.ntt_plan_table_bytes("bn254_fr", 10) == 32 * ((1 << 10) + 3 * (1 << 10))
+    assert _lib.ntt_plan_table_bytes("bn254_fr", 10, log2_tile=10) == 32 * ((1 << 10) + 3 * (1 << 10))
     two = _lib.ntt_plan_table_bytes("bls12_381_fr", 20, twiddle_mode=2)
     one = _lib.ntt_plan_table_bytes("bls12_381_fr", 20, twiddle_mode=1)
     assert 0 < two < one
