@@ -1599,7 +1599,7 @@ namespace {
 constexpr int kScalarBits = 255;  // BLS12-381 Fr elements are below 2^255
 
 struct MsmLayout {
-  size_t digits, counts, offsets, cursors, entries, partial, buckets, level_a, level_b, total;
+  size_t digits, counts, offsets, ranks, entries, partial, buckets, level_a, level_b, total;
 };
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
@@ -1617,8 +1617,8 @@ MsmLayout msm_layout(const msm_bases* b) {
   off += round256(nb * sizeof(uint32_t));
   L.offsets = off;
   off += round256((nb + 1) * sizeof(uint32_t));
-  L.cursors = off;
-  off += round256(nb * sizeof(uint32_t));
+  L.ranks = off;
+  off += round256(entries * sizeof(uint32_t));
   L.entries = off;
   off += round256(entries * sizeof(uint32_t));
   L.partial = off;
@@ -1727,7 +1727,7 @@ int msm_compute(const msm_bases* b, const void* d_scalars, void* d_result, void*
   m.digits = reinterpret_cast<uint16_t*>(w + L.digits);
   m.counts = reinterpret_cast<uint32_t*>(w + L.counts);
   m.offsets = reinterpret_cast<uint32_t*>(w + L.offsets);
-  m.cursors = reinterpret_cast<uint32_t*>(w + L.cursors);
+  m.ranks = reinterpret_cast<uint32_t*>(w + L.ranks);
   m.entries = reinterpret_cast<uint32_t*>(w + L.entries);
   m.partial = reinterpret_cast<uint32_t*>(w + L.partial);
   m.buckets = reinterpret_cast<uint32_t*>(w + L.buckets);

@@ -12,8 +12,9 @@
 //   window digits then all index one set of 2^c - 1 buckets, and the
 //   window-by-window Horner combination, a chain of W c point doublings that
 //   no amount of parallelism shortens, disappears from every MSM.
-// * Counting sort of (digit, point) pairs: a histogram of the digits, one
-//   scan and a scatter put the points of each bucket next to each other.
+// * Counting sort of (digit, point) pairs: a histogram of the digits (each
+//   entry keeps its rank in its bucket), one scan, and a scatter without
+//   atomics put the points of each bucket next to each other.
 // * Bucket accumulation: each bucket's points are split into S slices; one
 //   lane adds a slice's points into an XYZZ accumulator with mixed
 //   (XYZZ + affine) additions, 8 multiplications and 2 squarings each; the
@@ -21,9 +22,10 @@
 //   additions free of inversions.
 // * Bucket reduction by bits: sum_k k B_k = sum_b 2^b G_b with
 //   G_b = sum of the buckets whose index has bit b set.  The G_b are
-//   independent tree reductions (log depth, all lanes busy) and need only c
-//   doublings at the end, where the running-sum method is a serial chain of
-//   2^(c+1) additions.
+//   independent reductions (chunks of buckets per lane, then a tree in LDS
+//   per bit), and the c terms 2^b G_b are doubled in parallel and summed by a
+//   tree: a critical path of a few dozen point operations, where the
+//   running-sum method is a serial chain of 2^(c+1) additions.
 //
 // Field arithmetic: fq.hpp (12 x 32-bit limbs, Montgomery FIPS products).
 // Scalars arrive as the NTT library's Montgomery limbs over BLS12-381 Fr and
@@ -271,24 +273,27 @@ __device__ __forceinline__ uint32_t digit(const Fe& s, int c, int w) {
   return (uint32_t)(bits >> sh) & ((1u << c) - 1u);
 }
 
-// digits[w n + i] = window w of scalar i; counts[d] += 1 for each nonzero digit.
+// digits[w n + i] = window w of scalar i; for each nonzero digit d the entry
+// takes the next rank of bucket d (the histogram count before its increment),
+// so the scatter needs no atomics of its own.
 __global__ void __launch_bounds__(256) digits_kernel(const uint32_t* __restrict__ sc, uint64_t n, int c, int windows,
-                                                     uint16_t* __restrict__ digits, uint32_t* __restrict__ counts) {
+                                                     uint16_t* __restrict__ digits, uint32_t* __restrict__ ranks,
+                                                     uint32_t* __restrict__ counts) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const Fe s = scalar_plain(sc, i);
   for (int w = 0; w < windows; ++w) {
     const uint32_t d = digit(s, c, w);
-    digits[(uint64_t)w * n + i] = (uint16_t)d;
-    if (d) atomicAdd(counts + d, 1u);
+    const uint64_t e = (uint64_t)w * n + i;
+    digits[e] = (uint16_t)d;
+    if (d) ranks[e] = atomicAdd(counts + d, 1u);
   }
 }
 
 // Exclusive scan of counts[0 .. nb) into offsets[0 .. nb] (offsets[nb] =
-// total) and cursors (a copy of offsets for the scatter).  One workgroup of
-// 1024 threads, each summing a contiguous run.
+// total).  One workgroup of 1024 threads, each summing a contiguous run.
 __global__ void __launch_bounds__(1024) scan_kernel(const uint32_t* __restrict__ counts, uint32_t nb,
-                                                    uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursors) {
+                                                    uint32_t* __restrict__ offsets) {
   __shared__ uint32_t part[1024];
   const uint32_t t = threadIdx.x;
   const uint32_t per = (nb + 1023) / 1024;
@@ -306,22 +311,21 @@ __global__ void __launch_bounds__(1024) scan_kernel(const uint32_t* __restrict__
   uint32_t run = part[t] - s;  // exclusive prefix of this run
   for (uint32_t k = lo; k < hi; ++k) {
     offsets[k] = run;
-    cursors[k] = run;
     run += counts[k];
   }
   if (t == 1023) offsets[nb] = part[1023];
 }
 
-// entries[cursor[d]++] = w n + i for every nonzero digit d.
-__global__ void __launch_bounds__(256) scatter_kernel(const uint16_t* __restrict__ digits, uint64_t n, int windows,
-                                                      uint32_t* __restrict__ cursors, uint32_t* __restrict__ entries) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int w = 0; w < windows; ++w) {
-    const uint64_t e = (uint64_t)w * n + i;
-    const uint32_t d = digits[e];
-    if (d) entries[atomicAdd(cursors + d, 1u)] = (uint32_t)e;
-  }
+// entries[offsets[d] + rank] = w n + i for every nonzero digit d: one
+// thread per entry, no atomics.
+__global__ void __launch_bounds__(256) scatter_kernel(const uint16_t* __restrict__ digits,
+                                                      const uint32_t* __restrict__ ranks, uint64_t count,
+                                                      const uint32_t* __restrict__ offsets,
+                                                      uint32_t* __restrict__ entries) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const uint32_t d = digits[e];
+  if (d) entries[offsets[d] + ranks[e]] = (uint32_t)e;
 }
 
 // ---------------------------------------------------------------------------
@@ -379,15 +383,44 @@ __global__ void __launch_bounds__(128) sum_level_kernel(const uint32_t* __restri
   store_xyzz(out, g, acc);
 }
 
-// result = sum_b 2^b G_b by Horner (one lane): G_b are `c` XYZZ points.
-__global__ void __launch_bounds__(64) horner_kernel(const uint32_t* __restrict__ G, int c, uint32_t* __restrict__ res) {
-  if (threadIdx.x != 0) return;
-  Xyzz acc = infinity();
-  for (int b = c - 1; b >= 0; --b) {
-    acc = dbl(acc);
-    acc = add(acc, load_xyzz(G, (uint64_t)b));
+// Tree sum in LDS of the workgroup's points p[t] (t < blockDim.x, a power of
+// two): log2(blockDim.x) rounds of pairwise additions.  Returns the total in
+// every thread.
+__device__ __forceinline__ Xyzz lds_tree_sum(const Xyzz& p, Xyzz* sh) {
+  const uint32_t t = threadIdx.x;
+  sh[t] = p;
+  __syncthreads();
+  for (uint32_t half = blockDim.x >> 1; half > 0; half >>= 1) {
+    if (t < half) sh[t] = add(sh[t], sh[t + half]);
+    __syncthreads();
   }
-  store_xyzz(res, 0, acc);
+  return sh[0];
+}
+
+// G_b for b = blockIdx.x: the sum of `len` partials of bit b, 256 lanes each
+// summing a strided share, then a tree.
+__global__ void __launch_bounds__(256) reduce_bit_kernel(const uint32_t* __restrict__ in, uint32_t len,
+                                                         uint32_t* __restrict__ out) {
+  __shared__ Xyzz sh[256];
+  const uint32_t b = blockIdx.x;
+  Xyzz acc = infinity();
+  for (uint32_t k = threadIdx.x; k < len; k += blockDim.x) acc = add(acc, load_xyzz(in, (uint64_t)b * len + k));
+  const Xyzz total = lds_tree_sum(acc, sh);
+  if (threadIdx.x == 0) store_xyzz(out, b, total);
+}
+
+// result = sum_b 2^b G_b (b < c <= 16): lane b doubles G_b b times, then a
+// tree sums the c scaled points.
+__global__ void __launch_bounds__(16) final_kernel(const uint32_t* __restrict__ G, int c, uint32_t* __restrict__ res) {
+  __shared__ Xyzz sh[16];
+  const int b = (int)threadIdx.x;
+  Xyzz p = infinity();
+  if (b < c) {
+    p = load_xyzz(G, (uint64_t)b);
+    for (int k = 0; k < b; ++k) p = dbl(p);
+  }
+  const Xyzz total = lds_tree_sum(p, sh);
+  if (threadIdx.x == 0) store_xyzz(res, 0, total);
 }
 
 __global__ void __launch_bounds__(256) zero_kernel(uint32_t* __restrict__ p, uint64_t words) {
@@ -415,13 +448,14 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (m.n) {
     hipLaunchKernelGGL(digits_kernel, dim3(blocks(m.n, 256)), dim3(256), 0, s, m.scalars, m.n, m.c, m.windows,
-                       m.digits, m.counts);
+                       m.digits, m.ranks, m.counts);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, m.counts, nb, m.offsets, m.cursors);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, m.counts, nb, m.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (m.n) {
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks(m.n, 256)), dim3(256), 0, s, m.digits, m.n, m.windows, m.cursors,
+    const uint64_t count = (uint64_t)m.windows * m.n;
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks(count, 256)), dim3(256), 0, s, m.digits, m.ranks, count, m.offsets,
                        m.entries);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -438,19 +472,10 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
   hipLaunchKernelGGL(bits_level0_kernel, dim3(blocks((uint64_t)m.c * T, 128)), dim3(128), 0, s, m.buckets, nb, 1u,
                      m.c, m.chunk, m.level_a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  uint32_t* in = m.level_a;
-  uint32_t* out = m.level_b;
-  while (T > 1) {
-    const uint32_t T2 = (T + m.chunk - 1) / m.chunk;
-    hipLaunchKernelGGL(sum_level_kernel, dim3(blocks((uint64_t)m.c * T2, 128)), dim3(128), 0, s, in, (uint32_t)m.c,
-                       T, m.chunk, out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    uint32_t* tmp = in;
-    in = out;
-    out = tmp;
-    T = T2;
-  }
-  hipLaunchKernelGGL(horner_kernel, dim3(1), dim3(64), 0, s, in, m.c, m.result);
+  // each bit's partials into G_b, then sum_b 2^b G_b
+  hipLaunchKernelGGL(reduce_bit_kernel, dim3(m.c), dim3(256), 0, s, m.level_a, T, m.level_b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(final_kernel, dim3(1), dim3(16), 0, s, m.level_b, m.c, m.result);
   return hipGetLastError();
 }
 

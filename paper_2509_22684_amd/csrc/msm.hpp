@@ -22,7 +22,7 @@ struct MsmLaunch {
   uint16_t* digits;         // windows x n
   uint32_t* counts;         // 2^c
   uint32_t* offsets;        // 2^c + 1
-  uint32_t* cursors;        // 2^c
+  uint32_t* ranks;          // windows x n: an entry's place in its bucket
   uint32_t* entries;        // windows x n
   uint32_t* partial;        // 2^c x slices XYZZ
   uint32_t* buckets;        // 2^c XYZZ
