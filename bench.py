@@ -101,7 +101,8 @@ def peaks_leg(dev) -> dict:
     out = {}
     for kind, iters in (("mad_u64_u32", 2048), ("fma_f64", 2048), ("add_u32", 2048), ("addc_u32", 1024),
                         ("mad_addc", 1024), ("mad_fma", 1024), ("mad_add", 1024), ("ffmul_bls12_381", 128),
-                        ("ffmul_k2", 192), ("ffmul_k4", 96), ("ffmul_f64", 96)):
+                        ("ffmul_k2", 192), ("ffmul_k4", 96), ("ffmul_f64", 96), ("ffmul_lazy", 128),
+                        ("ffmul_bn254", 128)):
         rate, ms = zk_microbench(kind, small, iters=iters, reps=5)
         out[kind] = {"per_s": rate, "ms_per_launch": ms, "iters": iters}
     big = torch.empty(1 << 26, 8, dtype=torch.int32, device=dev)  # 2 GiB: 1 GiB read, 1 GiB written
@@ -118,7 +119,7 @@ def peaks_leg(dev) -> dict:
         "fips_column_steps_T_per_s": out["mad_addc"]["per_s"] / 1e12,
         "mad_with_fma_f64_T_instr_per_s": out["mad_fma"]["per_s"] / 1e12,
         "mad_with_add_u32_T_instr_per_s": out["mad_add"]["per_s"] / 1e12,
-        "ffmul_G_per_s": {k: out[f"ffmul_{k}"]["per_s"] / 1e9 for k in ("bls12_381", "k2", "k4", "f64")},
+        "ffmul_G_per_s": {k: out[f"ffmul_{k}"]["per_s"] / 1e9 for k in ("bls12_381", "k2", "k4", "f64", "lazy", "bn254")},
         "hbm_copy_TB_per_s": out["copy"]["bytes_per_s"] / 1e12,
         "spec_issue_rate_T_per_s": spec / 1e12,
     }

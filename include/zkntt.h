@@ -372,6 +372,10 @@ int msm_compute(const msm_bases *b, const void *d_scalars, void *d_result, void 
  *                          ZK_MB_FFMUL_K4 interleave two and four
  *   ZK_MB_FFMUL_F64        Montgomery products/s over BLS12-381 Fr on the FP64 multiplier
  *                          (three per thread, four waves per SIMD)
+ *   ZK_MB_FFMUL_LAZY       as ZK_MB_FFMUL_BLS12_381 without the final conditional subtraction
+ *                          (operands and results in [0, 2p), as in the NTT passes)
+ *   ZK_MB_FFMUL_BN254      as ZK_MB_FFMUL_BLS12_381 over BN254 Fr (a modulus whose lowest
+ *                          limb is not 1: the reduction digit costs a full multiply-add)
  *   ZK_MB_MAD_FMA          instructions/s of v_mad_u64_u32 and v_fma_f64 interleaved (independent)
  *   ZK_MB_MAD_ADD          instructions/s of v_mad_u64_u32 and v_add_u32 interleaved (independent)
  *   ZK_MB_COPY             bytes/s read plus written by a streaming copy of the
@@ -393,7 +397,9 @@ typedef enum {
   ZK_MB_FFMUL_K4 = 8,
   ZK_MB_MAD_FMA = 9,
   ZK_MB_MAD_ADD = 10,
-  ZK_MB_FFMUL_F64 = 11
+  ZK_MB_FFMUL_F64 = 11,
+  ZK_MB_FFMUL_LAZY = 12,
+  ZK_MB_FFMUL_BN254 = 13
 } zk_microbench_kind;
 int zk_microbench(int kind, uint32_t iters, void *d_buf, size_t buf_bytes, void *stream, int reps,
                   double *ops_per_s, float *ms_per_launch);
@@ -401,9 +407,12 @@ int zk_microbench(int kind, uint32_t iters, void *d_buf, size_t buf_bytes, void 
 /* Element-wise Montgomery product, for checking the multipliers on their
  * own: out_i = a_i b_i 2^-256 mod p with variant 0 (the integer FIPS product
  * of every transform), a_i b_i 2^-288 mod p with variant 1 (the FP64
- * product of ZK_FLAG_FFMUL_FP64 plans, whose radix is 2^288).  Inputs
- * canonical, 256-byte aligned device arrays of n elements; asynchronous on
- * `stream`.  out may equal a or b. */
+ * product of ZK_FLAG_FFMUL_FP64 plans, whose radix is 2^288).  Variant 2 is
+ * the product the transforms' butterflies use, without its final
+ * subtraction: out_i is congruent to a_i b_i 2^-256 and lies in [0, 2p) for
+ * any eight-limb a_i and canonical b_i.  Inputs canonical (variant 2: b
+ * only), 256-byte aligned device arrays of n elements; asynchronous on
+ * `stream`.  out may equal a or b.  ZK_EUNSUPPORTED for another variant. */
 int zk_field_mul(int field, int variant, const void *d_a, const void *d_b, void *d_out, uint64_t n, void *stream);
 
 /* Thread-local description of the calling thread's last failure. */

@@ -334,7 +334,8 @@ def ntt_profile_passes(plan, kind: int, d_in, d_out, d_work=None, stream=None) -
 
 
 def zk_field_mul(field, variant: int, d_a, d_b, d_out, n: int | None = None, stream=None) -> None:
-    """out = a b 2^-256 (variant 0, integer) or a b 2^-288 (variant 1, FP64) mod p, element-wise."""
+    """out = a b 2^-256 (variant 0, integer) or a b 2^-288 (variant 1, FP64) mod p, element-wise;
+    variant 2: the integer product without its final subtraction (congruent, in [0, 2p))."""
     if n is None:
         n = d_a.shape[0]
     _check(lib().zk_field_mul(_field_id(field), variant, _ptr(d_a), _ptr(d_b), _ptr(d_out), n,
@@ -343,7 +344,7 @@ def zk_field_mul(field, variant: int, d_a, d_b, d_out, n: int | None = None, str
 
 MICROBENCH = {"mad_u64_u32": 0, "fma_f64": 1, "add_u32": 2, "addc_u32": 3, "mad_addc": 4,
               "ffmul_bls12_381": 5, "copy": 6, "ffmul_k2": 7, "ffmul_k4": 8, "mad_fma": 9, "mad_add": 10,
-              "ffmul_f64": 11}
+              "ffmul_f64": 11, "ffmul_lazy": 12, "ffmul_bn254": 13}
 
 
 def zk_microbench(kind: str, d_buf, iters: int = 256, reps: int = 5, stream=None, buf_bytes: int | None = None):

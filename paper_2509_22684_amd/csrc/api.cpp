@@ -861,7 +861,8 @@ int ntt_profile_passes(const ntt_plan* p, int kind, const void* d_in, void* d_ou
 
 int zk_field_mul(int field, int variant, const void* d_a, const void* d_b, void* d_out, uint64_t n, void* stream) {
   if (!field_adicity(field)) return fail(ZK_EUNSUPPORTED, "unknown field id " + std::to_string(field));
-  if (variant != 0 && variant != 1) return fail(ZK_EUNSUPPORTED, "variant must be 0 (integer) or 1 (FP64)");
+  if (variant < 0 || variant > 2)
+    return fail(ZK_EUNSUPPORTED, "variant must be 0 (integer), 1 (FP64) or 2 (integer, lazy)");
   if (n && (!d_a || !d_b || !d_out)) return fail(ZK_EINVAL, "null pointer");
   if ((n && (!aligned(d_a) || !aligned(d_b) || !aligned(d_out))))
     return fail(ZK_EINVAL, "pointers must be 256-byte aligned");

@@ -116,6 +116,44 @@ __host__ __device__ __forceinline__ Fe sub(const Fe& a, const Fe& b) {
   return d;
 }
 
+// 2p as eight limbs (p < 2^255 for all three fields).
+template <class F>
+struct TwoP {
+  static constexpr uint32_t limb(int j) { return (F::P[j] << 1) | (j ? F::P[j - 1] >> 31 : 0u); }
+  static constexpr uint32_t V[kLimbs] = {limb(0), limb(1), limb(2), limb(3), limb(4), limb(5), limb(6), limb(7)};
+};
+
+// Lazy FF_add / FF_sub on [0, 2p): a, b < 2p in, result < 2p out.  The sum
+// a + b < 4p can exceed 2^256 (BLS12-381 Fr has p > 2^254), so its carry-out
+// takes part in the choice: subtract 2p when the sum carried out or the
+// subtraction did not borrow.
+template <class F>
+__host__ __device__ __forceinline__ Fe add_lazy(const Fe& a, const Fe& b) {
+  Fe s, d;
+  unsigned int c = 0, br = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) s.v[j] = __builtin_addc(a.v[j], b.v[j], c, &c);
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_subc(s.v[j], TwoP<F>::V[j], br, &br);
+  const bool keep = br & (c ^ 1u);
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = keep ? s.v[j] : d.v[j];
+  return d;
+}
+
+// a - b, plus 2p when it borrowed: a - b lies in (-2p, 2p).
+template <class F>
+__host__ __device__ __forceinline__ Fe sub_lazy(const Fe& a, const Fe& b) {
+  Fe d;
+  unsigned int br = 0, c = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_subc(a.v[j], b.v[j], br, &br);
+  const uint32_t mask = 0u - br;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) d.v[j] = __builtin_addc(d.v[j], TwoP<F>::V[j] & mask, c, &c);
+  return d;
+}
+
 // t < 2p in eight limbs -> t mod p.
 template <class F>
 __host__ __device__ __forceinline__ Fe reduce_once(const uint32_t t[kLimbs]) {
@@ -126,6 +164,12 @@ __host__ __device__ __forceinline__ Fe reduce_once(const uint32_t t[kLimbs]) {
 #pragma unroll
   for (int j = 0; j < kLimbs; ++j) r.v[j] = br ? t[j] : d.v[j];
   return r;
+}
+
+// x < 2p -> x mod p.
+template <class F>
+__host__ __device__ __forceinline__ Fe canon(const Fe& x) {
+  return reduce_once<F>(x.v);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +245,12 @@ __device__ __forceinline__ uint32_t add_carry_ord(uint32_t x, uint64_t& co) {
   asm volatile("v_addc_co_u32_e64 %0, %1, %2, 0, %1" : "=v"(r), "+s"(co) : "v"(x));
   return r;
 }
+// 0 - x with the borrow (x != 0) left in co, ordered like the forms above.
+__device__ __forceinline__ uint32_t neg_borrow_ord(uint32_t x, uint64_t& co) {
+  uint32_t r;
+  asm volatile("v_sub_co_u32_e64 %0, %1, 0, %2" : "=v"(r), "+s"(co) : "v"(x));
+  return r;
+}
 // x + (carry bit of this lane)
 __device__ __forceinline__ uint32_t add_carry(uint32_t x, uint64_t ci) {
   uint32_t r;
@@ -209,7 +259,7 @@ __device__ __forceinline__ uint32_t add_carry(uint32_t x, uint64_t ci) {
   return r;
 }
 
-template <class F>
+template <class F, bool CANON = true>
 __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
   if constexpr (HasAltMul<F>::value) return F::mul(a, b);
   uint32_t m[kLimbs], r[kLimbs];
@@ -237,9 +287,19 @@ __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
       ZK_TERM_P(m[j], F::P[i - j]);
     }
     ZK_TERM(a.v[i], b.v[0]);
-    m[i] = (uint32_t)acc * F::INV;
-    ZK_TERM_P(m[i], F::P[0]);
-    acc = (acc >> 32) | ((uint64_t)hi << 32);
+    if constexpr (F::P[0] == 1u) {
+      // see mul_k: the digit's product is a borrow
+      uint64_t co;
+      uint32_t lo;
+      asm("v_sub_co_u32_e64 %0, %1, 0, %2" : "=v"(m[i]), "=s"(co) : "v"((uint32_t)acc));
+      asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(lo), "=s"(co) : "v"((uint32_t)(acc >> 32)), "s"(co));
+      hi = add_carry(hi, co);
+      acc = ((uint64_t)hi << 32) | lo;
+    } else {
+      m[i] = (uint32_t)acc * F::INV;
+      ZK_TERM_P(m[i], F::P[0]);
+      acc = (acc >> 32) | ((uint64_t)hi << 32);
+    }
     hi = 0;
   }
   // Columns 8..15 hold the result.
@@ -256,7 +316,12 @@ __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
   }
 #undef ZK_TERM
 #undef ZK_TERM_P
-  return reduce_once<F>(r);  // the result is below 2p
+  // the result is below 2p; CANON = false leaves it there (see mul_k)
+  if constexpr (CANON) return reduce_once<F>(r);
+  Fe o;
+#pragma unroll
+  for (int j = 0; j < kLimbs; ++j) o.v[j] = r[j];
+  return o;
 }
 // K independent Montgomery products r[k] = a[k] b[k], computed column by
 // column in lock step.  Each column of one product is a serial chain
@@ -266,7 +331,22 @@ __device__ __forceinline__ Fe mul(const Fe& a, const Fe& b) {
 // waits for, which hides the issue latency the single chain exposes and
 // removes the carry-hazard wait states.  The result of each product is
 // identical to mul().
-template <class F, int K>
+//
+// Moduli with p = 1 mod 2^32 (BLS12-381 Fr, BLS12-377 Fr: -p^-1 = -1 mod
+// 2^32) make the reduction digit m_i = -c mod 2^32 for a column c, and
+// c + m_i p_0 = c + m_i has a zero low word with a carry into bit 32 exactly
+// when c mod 2^32 != 0.  The digit's multiply-add and carry count then become
+// one subtraction whose borrow is that carry, added to the column's high word
+// as it becomes the next column's low word, which also saves the register
+// move of the shift.
+//
+// Lazy reduction (CANON = false): before its final subtraction the
+// Montgomery product is (a b + m p) / 2^256 < a b / 2^256 + p < b + p, so for
+// any eight-limb a and a canonical b (b < p: every table entry and constant)
+// it is below 2p, and the subtraction can be left out.  Data in the NTT
+// passes stays in [0, 2p) this way (add_lazy / sub_lazy below keep that
+// range) and is made canonical once, where it leaves the computation.
+template <class F, int K, bool CANON = true>
 __device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
   if constexpr (HasAltMul<F>::value) {
 #pragma unroll
@@ -295,13 +375,27 @@ __device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
       ZK_TERMS(m[k][j], F::P[i - j], mad_co_vs_ord);
     }
     ZK_TERMS(a[k].v[i], b[k].v[0], mad_co_vv_ord);
+    if constexpr (F::P[0] == 1u) {
+      uint32_t lo[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) m[k][i] = (uint32_t)acc[k] * F::INV;
-    ZK_TERMS(m[k][i], F::P[0], mad_co_vs_ord);
+      for (int k = 0; k < K; ++k) m[k][i] = neg_borrow_ord((uint32_t)acc[k], co[k]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
-      hi[k] = 0;
+      for (int k = 0; k < K; ++k) lo[k] = add_carry_ord((uint32_t)(acc[k] >> 32), co[k]);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        hi[k] = add_carry_ord(hi[k], co[k]);
+        acc[k] = ((uint64_t)hi[k] << 32) | lo[k];
+        hi[k] = 0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) m[k][i] = (uint32_t)acc[k] * F::INV;
+      ZK_TERMS(m[k][i], F::P[0], mad_co_vs_ord);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc[k] = (acc[k] >> 32) | ((uint64_t)hi[k] << 32);
+        hi[k] = 0;
+      }
     }
   }
 #pragma unroll
@@ -320,15 +414,22 @@ __device__ __forceinline__ void mul_k(Fe* r, const Fe* a, const Fe* b) {
   }
 #undef ZK_TERMS
 #pragma unroll
-  for (int k = 0; k < K; ++k) r[k] = reduce_once<F>(t[k]);
+  for (int k = 0; k < K; ++k) {
+    if constexpr (CANON) {
+      r[k] = reduce_once<F>(t[k]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kLimbs; ++j) r[k].v[j] = t[k][j];
+    }
+  }
 }
 #else
 // Host compilation pass: device code is parsed but never emitted here.
-template <class F>
+template <class F, bool CANON = true>
 __host__ __device__ inline Fe mul(const Fe& a, const Fe& b) {
   return mul_portable<F>(a, b);
 }
-template <class F, int K>
+template <class F, int K, bool CANON = true>
 __host__ __device__ inline void mul_k(Fe* r, const Fe* a, const Fe* b) {
   for (int k = 0; k < K; ++k) r[k] = mul_portable<F>(a[k], b[k]);
 }

@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kThreads) rate_kernel(uint32_t iters, uint32_t
 
 // Montgomery products of the NTT's field, K interleaved per thread (the pass
 // kernels interleave 2 to 4): x_k <- x_k y_k.
-template <class F, int K>
+template <class F, int K, bool CANON = true>
 __global__ void __launch_bounds__(kThreads) ffmul_kernel(uint32_t iters, uint32_t seed, uint64_t* __restrict__ out) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   Fe x[K], y[K];
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kThreads) ffmul_kernel(uint32_t iters, uint32_
       x[k].v[j] = (j == kLimbs - 1) ? (seed + gid + (uint32_t)k) & 0x0fffffffu : seed * 2654435761u + gid * (j + 1);
       y[k].v[j] = (j == kLimbs - 1) ? (gid * 7u + (uint32_t)k) & 0x0fffffffu : gid * 40503u + (uint32_t)(j * k);
     }
-  for (uint32_t it = 0; it < iters; ++it) mul_k<F, K>(x, x, y);
+  for (uint32_t it = 0; it < iters; ++it) mul_k<F, K, CANON>(x, x, y);
   uint64_t r = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -153,7 +153,7 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
   // eight 256-thread workgroups per CU (32 waves, 8 per SIMD); the products
   // run at the pass kernels' occupancy, four waves per SIMD
   const bool ffmul = kind == ZK_MB_FFMUL_BLS12_381 || kind == ZK_MB_FFMUL_K2 || kind == ZK_MB_FFMUL_K4 ||
-                     kind == ZK_MB_FFMUL_F64;
+                     kind == ZK_MB_FFMUL_F64 || kind == ZK_MB_FFMUL_LAZY || kind == ZK_MB_FFMUL_BN254;
   const uint32_t blocks = (uint32_t)cus * (ffmul ? 4u : 8u);
   const uint64_t lanes = (uint64_t)blocks * kThreads;
   double ops = 0;  // per launch
@@ -190,6 +190,12 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       case ZK_MB_FFMUL_K4:
         hipLaunchKernelGGL((ffmul_kernel<Bls12_381Fr, 4>), dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
         break;
+      case ZK_MB_FFMUL_LAZY:
+        hipLaunchKernelGGL((ffmul_kernel<Bls12_381Fr, 3, false>), dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
+        break;
+      case ZK_MB_FFMUL_BN254:
+        hipLaunchKernelGGL((ffmul_kernel<Bn254Fr, 3>), dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
+        break;
       case ZK_MB_FFMUL_F64:
         hipLaunchKernelGGL(ffmul_f64_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 7u, out);
         break;
@@ -219,6 +225,8 @@ extern "C" int zk_microbench(int kind, uint32_t iters, void* d_buf, size_t buf_b
       break;
     case ZK_MB_FFMUL_BLS12_381:
     case ZK_MB_FFMUL_F64:
+    case ZK_MB_FFMUL_LAZY:
+    case ZK_MB_FFMUL_BN254:
       ops = (double)lanes * iters * 3;
       break;
     case ZK_MB_FFMUL_K2:

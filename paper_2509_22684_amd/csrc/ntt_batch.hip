@@ -84,6 +84,8 @@ __device__ __forceinline__ void acquire_from_l2() {
 // 2^(log_tile - 2) shadow thread t mod 2^(log_tile - 2) and store nothing.
 // log_r and log_tile are wave-uniform; 2 <= log_r <= log_tile <= 11.  (Batch
 // jobs never carry kPassPostPointwise: the pointwise step is a job of its own.)
+// Like the pass kernels it keeps the data in [0, 2p) inside the tile and
+// stores canonical values, so the stored bytes are the same.
 template <class F>
 __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_tile, uint32_t tile, Fe* lds) {
   using detail::lds_slot;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_t
         hi[e - 2 * h] = load_fe(a.tw_hi, ex >> a.log_lo);
         lo[e - 2 * h] = load_fe(a.tw_lo, ex & lo_mask);
       });
-      detail::mul_many<F, 2, 2>(hi, lo);
+      detail::mul_many<F, 2, 2, true>(hi, lo);  // canonical: the factor of the next product
       detail::mul_many<F, 2, 2>(v + 2 * h, hi);
     });
   }
@@ -228,10 +230,10 @@ __device__ __forceinline__ void tile_dyn(const PassArgs& a, int log_r, int log_t
     });
     detail::mul_many<F, 4, kDynGroup>(v, w);
   }
-  if (writer) {
+  if (writer) {  // canonical out, as the pass kernels
     sfor<4>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      detail::store_fe(a.out, out_index(e), v[e]);
+      detail::store_fe(a.out, out_index(e), canon<F>(v[e]));
     });
   }
 }

@@ -72,7 +72,13 @@ __global__ void __launch_bounds__(256) field_mul_kernel(const Fe* __restrict__ a
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const Fe x = load_fe(a, i), y = load_fe(b, i);
-  store_fe(out, i, VARIANT == 1 ? mul_f64<F>(x, y) : mul<F>(x, y));
+  if constexpr (VARIANT == 2) {  // the pass kernels' lazy, ordered product
+    Fe r;
+    mul_k<F, 1, false>(&r, &x, &y);
+    store_fe(out, i, r);
+  } else {
+    store_fe(out, i, VARIANT == 1 ? mul_f64<F>(x, y) : mul<F>(x, y));
+  }
 }
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
@@ -100,11 +106,12 @@ hipError_t launch_pass(int field, int log_r, int log_tile, int log_e, const Pass
 
 hipError_t launch_field_mul(int field, int variant, const Fe* a, const Fe* b, Fe* out, uint64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (variant != 0 && variant != 1) return hipErrorInvalidValue;
+  if (variant < 0 || variant > 2) return hipErrorInvalidValue;
   const dim3 grid(blocks_for(n, 256)), block(256);
 #define ZK_FIELD_MUL(FT)                                                                          \
   if (variant == 0) hipLaunchKernelGGL((field_mul_kernel<FT, 0>), grid, block, 0, s, a, b, out, n); \
-  else hipLaunchKernelGGL((field_mul_kernel<FT, 1>), grid, block, 0, s, a, b, out, n);
+  else if (variant == 1) hipLaunchKernelGGL((field_mul_kernel<FT, 1>), grid, block, 0, s, a, b, out, n); \
+  else hipLaunchKernelGGL((field_mul_kernel<FT, 2>), grid, block, 0, s, a, b, out, n);
   if (field == Bls12_381Fr::ID) {
     ZK_FIELD_MUL(Bls12_381Fr)
   } else if (field == Bn254Fr::ID) {

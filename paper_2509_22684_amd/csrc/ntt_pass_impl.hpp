@@ -18,7 +18,10 @@
 //     the pass reads its data ([r][j mod Ns]), so they stream coalesced
 //     alongside it; in-tile twiddles come from a small w_R table.
 //
-// All arithmetic is exact and branchless (see field.hpp).
+// All arithmetic is exact and branchless (see field.hpp).  Inside a pass the
+// data stays in [0, 2p) (lazy reduction: no final subtraction in the
+// products, butterflies that keep that range); every pass stores canonical
+// values, so buffers between passes and outputs hold canonical elements.
 #pragma once
 #include <utility>
 
@@ -91,20 +94,22 @@ constexpr int mul_group() {
   return EL >= 8 ? 2 : EL == 4 ? 3 : 4;
 }
 
-// x[k] = x[k] w[k] for k < N, in interleaved groups of GROUP products.
-template <class F, int N, int GROUP>
+// x[k] = x[k] w[k] for k < N, in interleaved groups of GROUP products.  The
+// w[k] are canonical (tables, constants); the products are left in [0, 2p)
+// (lazy reduction, field.hpp) unless CANON.
+template <class F, int N, int GROUP, bool CANON = false>
 __device__ __forceinline__ void mul_many(Fe* x, const Fe* w) {
   constexpr int G = N / GROUP, REST = N % GROUP;
   sfor<G>([&](auto g_) {
     constexpr int g = decltype(g_)::value;
-    mul_k<F, GROUP>(x + GROUP * g, x + GROUP * g, w + GROUP * g);
+    mul_k<F, GROUP, CANON>(x + GROUP * g, x + GROUP * g, w + GROUP * g);
   });
   if constexpr (REST == 1) {
     // a lone product keeps the reorderable form, which the scheduler can
     // overlap with surrounding loads and LDS traffic
-    x[GROUP * G] = mul<F>(x[GROUP * G], w[GROUP * G]);
+    x[GROUP * G] = mul<F, CANON>(x[GROUP * G], w[GROUP * G]);
   } else if constexpr (REST > 1) {
-    mul_k<F, REST>(x + GROUP * G, x + GROUP * G, w + GROUP * G);
+    mul_k<F, REST, CANON>(x + GROUP * G, x + GROUP * G, w + GROUP * G);
   }
 }
 
@@ -112,6 +117,7 @@ __device__ __forceinline__ void mul_many(Fe* x, const Fe* w) {
 // v[OFF .. OFF + E): bit-reversed renaming, then log2 E radix-2 DIT stages
 // with butterflies (x, y) -> (x + w y, x - w y).  W[k] = w_E^k for k < E/2.
 // The multiplications of one stage are independent and run interleaved.
+// Points in [0, 2p) in and out (lazy reduction).
 template <class F, int LOGE, int OFF, int N>
 __device__ __forceinline__ void dft_regs(Fe (&v)[N], const Fe* W) {
   constexpr int GROUP = mul_group<N>();
@@ -154,8 +160,8 @@ __device__ __forceinline__ void dft_regs(Fe (&v)[N], const Fe* W) {
         constexpr int b = (u >> st) << (st + 1);
         const Fe x = a[b + t];
         const Fe y = a[b + t + half];
-        a[b + t] = add<F>(x, y);
-        a[b + t + half] = sub<F>(x, y);
+        a[b + t] = add_lazy<F>(x, y);
+        a[b + t + half] = sub_lazy<F>(x, y);
       });
     });
     sfor<E>([&](auto s_) {
@@ -331,7 +337,7 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
         hi[k] = load_fe(a.tw_hi, ex >> a.log_lo);
         lo[k] = load_fe(a.tw_lo, ex & lo_mask);
       });
-      mul_many<F, CH, CH>(hi, lo);
+      mul_many<F, CH, CH, true>(hi, lo);  // canonical: the factor of the next product
       mul_many<F, CH, CH>(v + CH * h, hi);
     });
   }
@@ -372,13 +378,13 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
       constexpr int e = decltype(e_)::value;
       const uint64_t k = out_index(e);
       const Fe ab = mul<F>(load_fe(a.pw_a, k), load_fe(a.pw_b, k));
-      v[e] = mul<F>(sub<F>(ab, v[e]), a.post_const);
+      v[e] = mul<F>(sub<F>(ab, canon<F>(v[e])), a.post_const);
     });
   }
-  if (writer) {
+  if (writer) {  // canonical out of every pass
     sfor<S::EL>([&](auto e_) {
       constexpr int e = decltype(e_)::value;
-      store_fe(a.out, out_index(e), v[e]);
+      store_fe(a.out, out_index(e), canon<F>(v[e]));
     });
   }
 }
