@@ -76,9 +76,10 @@ typedef struct {
   uint32_t log2_radix;      /* radix of the in-register butterflies: 0 default (1, radix-2, up to
                                n = 2^18; 2 above), 1 (radix-2), 2 or 3 */
   uint32_t log2_tile;       /* elements per workgroup tile of a multi-pass transform, log2:
-                               0 default (8 for radix-2 transforms of n = 2^10 .. 2^16, else 10), 8 (small transforms over more CUs; register radix 2 or 4 only,
-                               passes of at most 2^7 points), 10 or 11 (2^11 tiles: twice the LDS,
-                               half the workgroups per CU) */
+                               0 default (8 for radix-2 transforms of n = 2^10 .. 2^16,
+                               else 10); 8 (small transforms over more CUs; register
+                               radix 2 or 4 only, passes of at most 2^7 points); 10; or
+                               11 (twice the LDS, half the workgroups per CU) */
   uint32_t flags;           /* ZK_FLAG_* */
   uint32_t log2_pass_radix; /* most butterfly stages fused into one global pass: 0 default (9 up to
                                n = 2^18, so at most two passes there; 8 above), 4..9 */

@@ -370,16 +370,34 @@ __device__ __forceinline__ void pass_tile(const PassArgs& a, uint64_t tile, Fe* 
   }
   if (a.flags & kPassPostPointwise) {
     // the quotient's pointwise step fused into the last pass of the third
-    // coset NTT: (A B - C) / (g^n - 1) with C this pass's output, in the
-    // same operation order as quotient_pointwise_kernel
-    // (one element at a time: this runs once per quotient, and holding the
-    // operands of all elements at once would cost registers everywhere)
-    sfor<S::EL>([&](auto e_) {
-      constexpr int e = decltype(e_)::value;
-      const uint64_t k = out_index(e);
-      const Fe ab = mul<F>(load_fe(a.pw_a, k), load_fe(a.pw_b, k));
-      v[e] = mul<F>(sub<F>(ab, canon<F>(v[e])), a.post_const);
-    });
+    // coset NTT: (A B - C) / (g^n - 1) with C this pass's output, one
+    // element at a time (this runs once per quotient).  Where the tile has
+    // LDS, the elements wait there (it is free after the last round) and
+    // come back one by one, so the step's operands never sit beside all of
+    // v: their register peak would otherwise be the whole kernel's and
+    // spill in every pass.
+    if constexpr (S::LDS_SLOTS >= S::THREADS * S::EL) {
+      __syncthreads();  // every thread has read its last round's inputs
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        lds[lds_slot(t * S::EL + e)] = v[e];
+      });
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        const uint64_t k = out_index(e);
+        const Fe ab = mul<F>(load_fe(a.pw_a, k), load_fe(a.pw_b, k));
+        const Fe r = mul<F>(sub_lazy<F>(ab, lds[lds_slot(t * S::EL + e)]), a.post_const);
+        if (writer) store_fe(a.out, k, r);
+      });
+      return;
+    } else {
+      sfor<S::EL>([&](auto e_) {
+        constexpr int e = decltype(e_)::value;
+        const uint64_t k = out_index(e);
+        const Fe ab = mul<F>(load_fe(a.pw_a, k), load_fe(a.pw_b, k));
+        v[e] = mul<F>(sub_lazy<F>(ab, v[e]), a.post_const);
+      });
+    }
   }
   if (writer) {  // canonical out of every pass
     sfor<S::EL>([&](auto e_) {
