@@ -310,13 +310,13 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0, 1.25, 1.5)) -> dict:
     def run(rate: float, budget: int) -> dict:
         specs = si.serve_jobs(master=5, njobs=njobs, rate_per_s=rate)
         reqs = [Request(s.job_id, s.log2n, s.arrival_s, pool[s.log2n]) for s in specs]
-        ex.ticks = ex.tick_jobs = 0
+        ex.ticks = ex.tick_jobs = ex.whole_jobs = 0
         srv = QuotientServer(ex, budget_bytes=budget)
         res = srv.run(reqs, realtime=True)
         out = summarize(res, solo_s)
         out.update({"rate_per_s": rate, "budget_bytes": budget, "ticks": ex.ticks,
-                    "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "max_inflight": srv.max_inflight,
-                    "peak_bytes": srv.peak_bytes})
+                    "mean_jobs_per_tick": ex.tick_jobs / max(1, ex.ticks), "jobs_run_whole": ex.whole_jobs,
+                    "max_inflight": srv.max_inflight, "peak_bytes": srv.peak_bytes})
         return out
 
     run(mu, 200 << 30)  # warm-up
@@ -327,7 +327,8 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0, 1.25, 1.5)) -> dict:
     admission = dict(rho=1.0, **run(mu, 2 << 30))
     return {"workload": f"{njobs} quotient jobs, log2 n uniform in [14,22] (seed 5), BLS12-381 Fr, Poisson arrivals "
                         "at rho x solo throughput",
-            "lanes": {"bounds_log2n": list(ex.lane_bounds), "ticks_enqueued_ahead": 2},
+            "lanes": {"bounds_log2n": list(ex.lane_bounds), "ticks_enqueued_ahead": 2,
+                      "lone_job_runs_whole_chain": True},
             "mu_solo_jobs_per_s": mu, "solo_ms_by_log2n": {str(L): t * 1e3 for L, t in solo_s.items()},
             "runs": runs, "admission_2GB": admission}
 

@@ -19,6 +19,13 @@ own sequence of ticks, so the long stages of large jobs (which fill the chip
 by themselves) do not hold back the next stage of small ones; the lanes'
 launches overlap on the device.
 
+A lone job runs whole.  When a lane holds a single job that has not
+started, its tick is that job's whole chain as one quotient_poly call (A's
+and B's chains on forked streams, the pointwise step fused): at light load
+a job then costs its stand-alone time instead of four batch builds and four
+dependent ticks.  As soon as two jobs overlap in a lane they share batched
+ticks again.
+
 No host wait per tick.  A lane keeps up to `depth` ticks enqueued: tick k+1
 (every job's next stage, in stream order after tick k) is built and launched
 while tick k runs, and completions are found by polling the ticks' events,
@@ -94,6 +101,7 @@ class GpuExecutor:
         self.max_log2n = FIELD_ADICITY.get(field, 47)
         self.ticks = 0
         self.tick_jobs = 0
+        self.whole_jobs = 0
         with torch.cuda.device(self.device):
             _register_tuning_for_current_device()  # plans and their sizes follow the tuned schedules
 
@@ -188,6 +196,27 @@ class GpuExecutor:
         self.tick_jobs += len(items)
         return (b, ev)
 
+    def enqueue_whole(self, lane: int, h):
+        """One job's whole quotient chain as one quotient_poly call on the
+        lane's stream (after its uploads); the job's T1, T2 and workspace
+        vectors, contiguous, are the chain's workspace.  Does not wait."""
+        from ._lib import quotient_poly, quotient_workspace_bytes
+
+        stream = self.streams[lane]
+        stream.wait_event(h["ready"])
+        p = h["plan"]
+        n = h["A"].shape[0]
+        work = h["bufs"][4 * n:]  # T1, T2, W1, W2, W3: 5 n elements
+        assert quotient_workspace_bytes(p.handle) <= work.numel() * 4
+        with self.torch.cuda.device(self.device):
+            quotient_poly(p.handle, h["A"], h["B"], h["C"], h["H"], work, stream)
+            ev = self.torch.cuda.Event()
+            ev.record(stream)
+        self.ticks += 1
+        self.tick_jobs += 1
+        self.whole_jobs += 1
+        return (None, ev)
+
     @staticmethod
     def tick_done(token) -> bool:
         return token[1].query()
@@ -197,6 +226,8 @@ class GpuExecutor:
         from ._lib import ntt_batch_destroy, ntt_batch_status
 
         b, _ = token
+        if b is None:  # a whole job: quotient_poly reports errors when called
+            return
         try:
             rc = ntt_batch_status(b)
         finally:
@@ -305,6 +336,13 @@ class QuotientServer:
                             used -= ex.job_bytes(job.req.log2n)
                             results[job.req.job_id] = job.res
                             ln["jobs"].remove(job)
+                # a lone job that has not started runs its whole chain at once
+                whole = getattr(ex, "enqueue_whole", None)
+                if whole and len(ln["jobs"]) == 1 and ln["jobs"][0].next_stage == 0 and len(ln["ticks"]) < self.depth:
+                    job = ln["jobs"][0]
+                    ln["ticks"].append(_Tick(whole(li, job.handle), [(job, STAGES - 1)]))
+                    job.next_stage = STAGES
+                    progress = True
                 # keep up to `depth` ticks enqueued: each advances every job
                 # of the lane that has a stage left by one stage
                 while len(ln["ticks"]) < self.depth:

@@ -202,3 +202,66 @@ def test_summary_slowdown_against_solo():
     res = QuotientServer(ex, budget_bytes=1 << 30).run(reqs, realtime=False)
     s = summarize(res, solo_s={4: 1.0, 5: 1.0})
     assert s["p50_slowdown"] >= 0 and set(s["by_log2n"]) == {"4", "5"}
+
+
+class WholeOracleExecutor(OracleExecutor):
+    """Also offers the whole-chain path: a lone job's quotient in one tick."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.whole = []
+
+    def enqueue_whole(self, lane, h):
+        assert self.lane_of(h["req"].log2n) == lane
+        self.whole.append(h["req"].job_id)
+        return self.enqueue_tick(lane, [(h, STAGES - 1)])
+
+
+def test_lone_job_runs_its_whole_chain_in_one_tick():
+    reqs = make_requests([5])
+    ex = WholeOracleExecutor()
+    res = QuotientServer(ex, budget_bytes=1 << 30).run(reqs, realtime=False)
+    check_results(res, reqs)
+    assert ex.whole == [0] and ex.ticks == [[(0, STAGES - 1)]]
+
+
+def test_overlapping_jobs_share_batched_ticks_not_whole_chains():
+    """Jobs admitted together in one lane batch their stages; alone in their
+    lanes they run whole."""
+    reqs = make_requests([5, 5, 5])
+    ex = WholeOracleExecutor()
+    res = QuotientServer(ex, budget_bytes=1 << 30).run(reqs, realtime=False)
+    check_results(res, reqs)
+    assert ex.whole == [] and len(ex.ticks) == STAGES and all(len(t) == 3 for t in ex.ticks)
+    reqs2 = make_requests([4, 8])
+    ex2 = WholeOracleExecutor(lane_bounds=(6,))
+    res2 = QuotientServer(ex2, budget_bytes=1 << 30).run(reqs2, realtime=False)
+    check_results(res2, reqs2)
+    assert sorted(ex2.whole) == [0, 1]
+
+
+def test_job_arriving_during_a_whole_chain_is_batched_after_it():
+    """A second job that arrives while the first runs whole finds the lane
+    busy (one job in it) and starts with ordinary ticks; both finish with the
+    oracle's results."""
+
+    class SteppedClock:
+        def __init__(self):
+            self.t = 0.0
+
+        def __call__(self):
+            return self.t
+
+    clock = SteppedClock()
+    reqs = make_requests([5, 5], gaps=[0.5, 0.0])
+
+    class Ticking(WholeOracleExecutor):
+        def enqueue_tick(self, lane, items):
+            clock.t += 1.0
+            return super().enqueue_tick(lane, items)
+
+    ex = Ticking(complete_after=2)
+    res = QuotientServer(ex, budget_bytes=1 << 30, clock=clock, poll_s=0).run(reqs, realtime=True)
+    check_results(res, reqs)
+    assert ex.whole == [0]
+    assert sorted(st for t in ex.ticks for j, st in t if j == 1) == list(range(STAGES))
