@@ -1364,7 +1364,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     b->direct.push_back(std::move(d));
   }
   // Next to direct work the persistent kernel takes one workgroup per CU,
-  // leaving LDS and wave slots for the pass kernels beside it.
+  // leaving LDS and wave slots for the pass kernels beside it (below: half
+  // of that when its items can wait).
   const bool beside = !b->direct.empty() && !items.empty();
   b->grid = (uint32_t)std::min<size_t>(items.size(), (size_t)cus * (beside ? 1 : zk::batch_workgroups_per_cu()));
   // Direct work goes to up to kSideStreams side streams, dealt largest first
@@ -1386,6 +1387,29 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
       const size_t l = (size_t)(std::min_element(lane_load.begin(), lane_load.end()) - lane_load.begin());
       b->direct[i].lane = l;
       lane_load[l] += work[i];
+    }
+    // Beside direct work whose longest lane takes longer than the persistent
+    // kernel would on half the CUs, the persistent kernel gets half the CUs:
+    // its items have slack, and the freed slots go to the direct pass
+    // launches, whose chain of dependent passes is then the batch's critical
+    // path.  (64-job batch: 0.512-0.520 against 0.543 ms; below half the
+    // CUs it measured flat.)  Lane times use the estimate above; the
+    // persistent kernel's is allowed twice the longest lane's, since that
+    // estimate counts a pass alone on the chip.
+    if (beside) {
+      std::vector<double> lane_us(nsides, 0.0);
+      for (const DirectWork& d : b->direct) {
+        if (d.pointwise) continue;
+        const int log_tile = d.plan->passes[0].log_tile;
+        const double tiles = (double)(d.plan->n >> log_tile) * std::max<uint32_t>(1, d.pass[0].grp_jobs);
+        const double slots = (double)cus * (log_tile >= 11 ? 2 : 4);
+        lane_us[d.lane] += (double)d.pass.size() *
+                           (kLaunchUs + std::ceil(tiles / slots) * kRoundUs * std::ldexp(1.0, log_tile - 10));
+      }
+      const double longest = *std::max_element(lane_us.begin(), lane_us.end());
+      const uint32_t half = (uint32_t)std::max(1, cus / 2);
+      if ((double)items.size() * kBatchItemUs / half <= 2.0 * longest)
+        b->grid = std::min<uint32_t>(b->grid, half);
     }
     b->sides.assign(nsides, nullptr);
     b->joins.assign(nsides, nullptr);
