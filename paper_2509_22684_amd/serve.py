@@ -207,7 +207,8 @@ class GpuExecutor:
         p = h["plan"]
         n = h["A"].shape[0]
         work = h["bufs"][4 * n:]  # T1, T2, W1, W2, W3: 5 n elements
-        assert quotient_workspace_bytes(p.handle) <= work.numel() * 4
+        if quotient_workspace_bytes(p.handle) > work.numel() * 4:
+            raise RuntimeError("quotient workspace larger than a job's spare vectors")
         with self.torch.cuda.device(self.device):
             quotient_poly(p.handle, h["A"], h["B"], h["C"], h["H"], work, stream)
             ev = self.torch.cuda.Event()
