@@ -356,7 +356,9 @@ size_t msm_bases_device_bytes(const msm_bases *b);
 size_t msm_workspace_bytes(const msm_bases *b);
 /* d_result = sum_i s_i P_i for the n scalars at d_scalars; asynchronous on
  * `stream`.  d_work: msm_workspace_bytes(b) bytes; concurrent calls need
- * their own workspace.  Inputs are not modified. */
+ * their own workspace.  Inputs are not modified.  ZK_EINVAL: null or
+ * misaligned pointers, scalars, result and workspace overlapping (byte
+ * ranges), or a current device other than the one the bases live on. */
 int msm_compute(const msm_bases *b, const void *d_scalars, void *d_result, void *d_work, void *stream);
 
 /* Measurement helper: the all-CU rate of the units the NTT's rooflines are

@@ -1735,11 +1735,17 @@ int msm_compute(const msm_bases* b, const void* d_scalars, void* d_result, void*
   if (!d_scalars || !d_result || !d_work) return fail(ZK_EINVAL, "null pointer");
   if (!aligned(d_scalars) || !aligned(d_result) || !aligned(d_work))
     return fail(ZK_EINVAL, "pointers must be 256-byte aligned");
+  const MsmLayout L = msm_layout(b);
+  {
+    const size_t sb = b->n * 8 * sizeof(uint32_t), rb = zk::msm::kXyzzWords * sizeof(uint32_t);
+    if (overlaps(d_work, L.total, d_scalars, sb) || overlaps(d_result, rb, d_scalars, sb) ||
+        overlaps(d_result, rb, d_work, L.total))
+      return fail(ZK_EINVAL, "scalars, result and workspace must not overlap");
+  }
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != b->device) return fail(ZK_EINVAL, "the current HIP device is not the bases' device");
-  const MsmLayout L = msm_layout(b);
   char* w = static_cast<char*>(d_work);
   zk::msm::MsmLaunch m{};
   m.table = static_cast<const uint32_t*>(b->table);

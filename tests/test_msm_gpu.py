@@ -121,3 +121,24 @@ def test_msm_2_20_closed_form(cuda, multiples_g):
     scal = [rng.randrange(FR.p) for _ in range(n)]
     got, _ = _run(mults, scal, cuda)
     assert got == M.mul(sum(s * (i + 1) for i, s in enumerate(scal)) % FR.p, G)
+
+
+def test_msm_argument_checks(cuda, small_points):
+    """Overlapping result, workspace and scalars, and misaligned pointers, are
+    refused before anything runs."""
+    import torch
+
+    from paper_2509_22684_amd import ZkError
+
+    pts = small_points[:4]
+    _, bases = _run(pts, [1, 2, 3, 4], cuda)
+    scal = _scalars_dev([5, 6, 7, 8], cuda)
+    work = bases.workspace()
+    for out, w in ((work.view(-1)[:64], None), (scal.view(-1)[:64], None), (None, scal.view(-1, 8))):
+        with pytest.raises(ZkError) as e:
+            bases.msm(scal, out=out, work=w)
+        assert e.value.code == -1
+    big = torch.zeros(4 * 8 + 64, dtype=torch.int32, device=cuda)
+    with pytest.raises(ZkError) as e:  # scalars 4 bytes past a 256-byte boundary
+        bases.msm(big[1:33].view(4, 8))
+    assert e.value.code == -1
