@@ -76,3 +76,21 @@ def test_serving_sizes_up_to_2_22(cuda):
     for r, q in zip(res, reqs):
         assert r.status == "done"
         assert np.array_equal(to_host(r.H), coracle.quotient(FIELD, *q.inputs)), f"job {q.job_id} (2^{q.log2n})"
+
+
+def test_lone_jobs_run_whole_and_match(cuda):
+    """A job alone in its lane runs its whole chain as one quotient_poly call
+    on the job's own buffers; its H equals the oracle's and the stand-alone
+    call's.  Jobs sharing a lane still go through batched ticks."""
+    from paper_2509_22684_amd.serve import GpuExecutor, QuotientServer
+
+    reqs = _requests([12, 20, 13, 13])  # lanes by 2^19: {12, 13, 13} and {20}
+    ex = GpuExecutor(FIELD)
+    res = QuotientServer(ex, budget_bytes=200 << 30).run(reqs, realtime=False)
+    assert ex.whole_jobs == 1  # the 2^20 job; the three small ones share ticks
+    _check(res, reqs, cuda)
+    reqs1 = _requests([15])
+    ex1 = GpuExecutor(FIELD)
+    res1 = QuotientServer(ex1, budget_bytes=200 << 30).run(reqs1, realtime=False)
+    assert ex1.whole_jobs == 1 and ex1.ticks == 1
+    _check(res1, reqs1, cuda)
