@@ -1615,7 +1615,7 @@ struct msm_bases {
   int c = 0;
   int windows = 0;
   uint32_t slices = 1;
-  uint32_t chunk = 16;
+  uint32_t chunk = 8;
   void* table = nullptr;
 };
 

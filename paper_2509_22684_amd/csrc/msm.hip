@@ -350,9 +350,9 @@ __global__ void __launch_bounds__(128) accumulate_kernel(const uint32_t* __restr
 
 // ---------------------------------------------------------------------------
 // Reduction by bits.  Level 0: lane (b, t) sums, over buckets d of chunk t
-// (chunk = `chunk` consecutive bucket indices) with bit b of d set, the S
-// slices of those buckets; out[b * T + t].  Later levels sum `chunk`
-// consecutive partials of each b.
+// (chunk = `chunk` consecutive bucket indices, 8: a lane adds at most 8
+// buckets, the chunk's all when bit b lies above the chunk's bits) with bit
+// b of d set, the S slices of those buckets; out[b * T + t].
 
 __global__ void __launch_bounds__(128) bits_level0_kernel(const uint32_t* __restrict__ partial, uint32_t nb,
                                                           uint32_t slices, int c, uint32_t chunk,
@@ -397,11 +397,12 @@ __device__ __forceinline__ Xyzz lds_tree_sum(const Xyzz& p, Xyzz* sh) {
   return sh[0];
 }
 
-// G_b for b = blockIdx.x: the sum of `len` partials of bit b, 256 lanes each
-// summing a strided share, then a tree.
-__global__ void __launch_bounds__(256) reduce_bit_kernel(const uint32_t* __restrict__ in, uint32_t len,
-                                                         uint32_t* __restrict__ out) {
-  __shared__ Xyzz sh[256];
+// G_b for b = blockIdx.x: the sum of `len` partials of bit b, 512 lanes each
+// summing a strided share, then a tree (96 KiB of LDS).
+constexpr int kReduceThreads = 512;
+__global__ void __launch_bounds__(kReduceThreads) reduce_bit_kernel(const uint32_t* __restrict__ in, uint32_t len,
+                                                                    uint32_t* __restrict__ out) {
+  __shared__ Xyzz sh[kReduceThreads];
   const uint32_t b = blockIdx.x;
   Xyzz acc = infinity();
   for (uint32_t k = threadIdx.x; k < len; k += blockDim.x) acc = add(acc, load_xyzz(in, (uint64_t)b * len + k));
@@ -473,7 +474,7 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
                      m.c, m.chunk, m.level_a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // each bit's partials into G_b, then sum_b 2^b G_b
-  hipLaunchKernelGGL(reduce_bit_kernel, dim3(m.c), dim3(256), 0, s, m.level_a, T, m.level_b);
+  hipLaunchKernelGGL(reduce_bit_kernel, dim3(m.c), dim3(kReduceThreads), 0, s, m.level_a, T, m.level_b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(final_kernel, dim3(1), dim3(16), 0, s, m.level_b, m.c, m.result);
   return hipGetLastError();
