@@ -352,7 +352,10 @@ void msm_bases_destroy(msm_bases *b);
 uint64_t msm_bases_count(const msm_bases *b);
 int msm_bases_window_bits(const msm_bases *b);
 size_t msm_bases_device_bytes(const msm_bases *b);
-/* Bytes of workspace msm_compute needs (sort arrays and bucket sums). */
+/* Bytes of workspace msm_compute needs: the sort arrays, one bucket
+ * histogram per group of 65535 / W scalars, and the bucket sums, with one
+ * accumulator pair per accumulation lane (as many lanes as the bases' device
+ * keeps resident at once). */
 size_t msm_workspace_bytes(const msm_bases *b);
 /* d_result = sum_i s_i P_i for the n scalars at d_scalars; asynchronous on
  * `stream`.  d_work: msm_workspace_bytes(b) bytes; concurrent calls need

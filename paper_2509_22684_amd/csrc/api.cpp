@@ -1614,8 +1614,10 @@ struct msm_bases {
   uint64_t n = 0;
   int c = 0;
   int windows = 0;
-  uint32_t slices = 1;
-  uint32_t chunk = 8;
+  uint32_t per_group = 1;  // scalars per histogram group
+  uint32_t groups = 1;
+  uint32_t lanes = 1;      // accumulation lanes
+  uint32_t kmin = 32;      // fewest sorted entries per accumulation lane
   void* table = nullptr;
 };
 
@@ -1624,7 +1626,7 @@ namespace {
 constexpr int kScalarBits = 255;  // BLS12-381 Fr elements are below 2^255
 
 struct MsmLayout {
-  size_t digits, counts, offsets, ranks, entries, partial, buckets, level_a, level_b, total;
+  size_t digits, ranks, hist, counts, offsets, entries, head, tail, buckets, chunk_sums, level_a, level_b, total;
 };
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
@@ -1633,27 +1635,34 @@ MsmLayout msm_layout(const msm_bases* b) {
   MsmLayout L{};
   const size_t nb = size_t(1) << b->c;
   const size_t entries = (size_t)b->windows * b->n;
-  const size_t T = (nb + b->chunk - 1) / b->chunk;
+  const size_t T = (nb + zk::msm::kChunk - 1) / zk::msm::kChunk;
+  const size_t T0 = (T + zk::msm::kLevel0Lanes - 1) / zk::msm::kLevel0Lanes;
   const size_t xyzz = zk::msm::kXyzzWords * sizeof(uint32_t);
   size_t off = 0;
   L.digits = off;
   off += round256(entries * sizeof(uint16_t));
+  L.ranks = off;
+  off += round256(entries * sizeof(uint16_t));
+  L.hist = off;
+  off += round256((size_t)b->groups * nb * sizeof(uint32_t));
   L.counts = off;
   off += round256(nb * sizeof(uint32_t));
   L.offsets = off;
   off += round256((nb + 1) * sizeof(uint32_t));
-  L.ranks = off;
-  off += round256(entries * sizeof(uint32_t));
   L.entries = off;
   off += round256(entries * sizeof(uint32_t));
-  L.partial = off;
-  off += round256(nb * b->slices * xyzz);
+  L.head = off;
+  off += round256((size_t)b->lanes * xyzz);
+  L.tail = off;
+  off += round256((size_t)b->lanes * xyzz);
   L.buckets = off;
   off += round256(nb * xyzz);
+  L.chunk_sums = off;
+  off += round256(T * xyzz);
   L.level_a = off;
-  off += round256((size_t)b->c * T * xyzz);
+  off += round256((size_t)b->c * T0 * xyzz);
   L.level_b = off;
-  off += round256((size_t)b->c * T * xyzz);
+  off += round256((size_t)b->c * xyzz);
   L.total = off;
   return L;
 }
@@ -1686,7 +1695,18 @@ int msm_bases_create(msm_bases** out, const void* d_points, uint64_t n, uint32_t
   b->n = n;
   b->c = c;
   b->windows = windows;
-  b->slices = std::max<uint32_t>(1, (1u << 18) >> c);
+  // histogram groups: per_group x windows digits, each bucket's count in a
+  // group below 2^16
+  b->per_group = (uint32_t)std::min<uint64_t>(n, 65535u / (uint32_t)windows);
+  b->groups = (uint32_t)((n + b->per_group - 1) / b->per_group);
+  // accumulation lanes: the resident ones, fewer when the entries are few
+  e = zk::msm::accumulate_lanes(&b->lanes);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "accumulation occupancy");
+  }
+  b->lanes = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(b->lanes, ((uint64_t)windows * n + b->kmin - 1) / b->kmin));
   const size_t table_bytes = (size_t)windows * n * zk::msm::kPointWords * sizeof(uint32_t);
   e = hipMalloc(&b->table, table_bytes);
   if (e != hipSuccess) {
@@ -1753,15 +1773,20 @@ int msm_compute(const msm_bases* b, const void* d_scalars, void* d_result, void*
   m.n = b->n;
   m.c = b->c;
   m.windows = b->windows;
-  m.slices = b->slices;
-  m.chunk = b->chunk;
+  m.per_group = b->per_group;
+  m.groups = b->groups;
+  m.lanes = b->lanes;
+  m.kmin = b->kmin;
   m.digits = reinterpret_cast<uint16_t*>(w + L.digits);
+  m.ranks = reinterpret_cast<uint16_t*>(w + L.ranks);
+  m.hist = reinterpret_cast<uint32_t*>(w + L.hist);
   m.counts = reinterpret_cast<uint32_t*>(w + L.counts);
   m.offsets = reinterpret_cast<uint32_t*>(w + L.offsets);
-  m.ranks = reinterpret_cast<uint32_t*>(w + L.ranks);
   m.entries = reinterpret_cast<uint32_t*>(w + L.entries);
-  m.partial = reinterpret_cast<uint32_t*>(w + L.partial);
+  m.head = reinterpret_cast<uint32_t*>(w + L.head);
+  m.tail = reinterpret_cast<uint32_t*>(w + L.tail);
   m.buckets = reinterpret_cast<uint32_t*>(w + L.buckets);
+  m.chunk_sums = reinterpret_cast<uint32_t*>(w + L.chunk_sums);
   m.level_a = reinterpret_cast<uint32_t*>(w + L.level_a);
   m.level_b = reinterpret_cast<uint32_t*>(w + L.level_b);
   m.result = static_cast<uint32_t*>(d_result);

@@ -12,14 +12,16 @@
 //   window digits then all index one set of 2^c - 1 buckets, and the
 //   window-by-window Horner combination, a chain of W c point doublings that
 //   no amount of parallelism shortens, disappears from every MSM.
-// * Counting sort of (digit, point) pairs: a histogram of the digits (each
-//   entry keeps its rank in its bucket), one scan, and a scatter without
-//   atomics put the points of each bucket next to each other.
-// * Bucket accumulation: each bucket's points are split into S slices; one
-//   lane adds a slice's points into an XYZZ accumulator with mixed
-//   (XYZZ + affine) additions, 8 multiplications and 2 squarings each; the
-//   slices then combine.  XYZZ coordinates (x = X / ZZ, y = Y / ZZZ) keep
-//   additions free of inversions.
+// * Counting sort of (digit, point) pairs: per-workgroup histograms in LDS
+//   (each entry keeps its rank within its group and bucket), a prefix over
+//   the groups per bucket, one scan over the buckets, and a scatter put the
+//   points of each bucket next to each other, with no global atomics.
+// * Bucket accumulation: the sorted entries are cut into equal runs, one per
+//   lane, across bucket boundaries; a lane adds its run's points into XYZZ
+//   accumulators with mixed (XYZZ + affine) additions, 8 multiplications
+//   and 2 squarings each, and the segments at the runs' ends then combine
+//   per bucket.  XYZZ coordinates (x = X / ZZ, y = Y / ZZZ) keep additions
+//   free of inversions.
 // * Bucket reduction by bits: sum_k k B_k = sum_b 2^b G_b with
 //   G_b = sum of the buckets whose index has bit b set.  The G_b are
 //   independent reductions (chunks of buckets per lane, then a tree in LDS
@@ -32,6 +34,7 @@
 // are converted with one product by 1.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "field.hpp"
@@ -265,122 +268,235 @@ __device__ __forceinline__ Fe scalar_plain(const uint32_t* __restrict__ sc, uint
   return mul<Bls12_381Fr>(s, one);
 }
 
+// Bits [c w, c w + c) of s.  The limbs are picked by unrolled selects, not
+// by a run-time index, so s stays in registers.
 __device__ __forceinline__ uint32_t digit(const Fe& s, int c, int w) {
   const int lo = c * w;
   const int word = lo >> 5, sh = lo & 31;
-  uint64_t bits = s.v[word];
-  if (word + 1 < kLimbs) bits |= (uint64_t)s.v[word + 1] << 32;
+  uint32_t w0 = 0u, w1 = 0u;
+#pragma unroll
+  for (int k = 0; k < kLimbs; ++k) {
+    w0 = k == word ? s.v[k] : w0;
+    w1 = k == word + 1 ? s.v[k] : w1;
+  }
+  const uint64_t bits = ((uint64_t)w1 << 32) | w0;
   return (uint32_t)(bits >> sh) & ((1u << c) - 1u);
 }
 
-// digits[w n + i] = window w of scalar i; for each nonzero digit d the entry
-// takes the next rank of bucket d (the histogram count before its increment),
-// so the scatter needs no atomics of its own.
-__global__ void __launch_bounds__(256) digits_kernel(const uint32_t* __restrict__ sc, uint64_t n, int c, int windows,
-                                                     uint16_t* __restrict__ digits, uint32_t* __restrict__ ranks,
-                                                     uint32_t* __restrict__ counts) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Fe s = scalar_plain(sc, i);
-  for (int w = 0; w < windows; ++w) {
-    const uint32_t d = digit(s, c, w);
-    const uint64_t e = (uint64_t)w * n + i;
-    digits[e] = (uint16_t)d;
-    if (d) ranks[e] = atomicAdd(counts + d, 1u);
+// Counting sort without global atomics.  Workgroup g takes scalars
+// [g B, g B + B) with B windows <= 65535, so that each bucket's count in the
+// group fits 16 bits: the group's histogram lives in LDS as 16-bit halves of
+// 32-bit words (2^c x 2 bytes, at most 128 KiB), and each digit's LDS
+// increment returns its rank among the group's digits of that bucket.
+// hist[g 2^c + d] = the group's count of digit d.
+constexpr int kHistThreads = 1024;
+constexpr uint32_t kHistWords = 1u << 15;  // 2^16 16-bit counters
+
+__global__ void __launch_bounds__(kHistThreads) hist_kernel(const uint32_t* __restrict__ sc, uint64_t n, int c,
+                                                            int windows, uint32_t per_group,
+                                                            uint16_t* __restrict__ digits, uint16_t* __restrict__ ranks,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kHistWords];
+  const uint32_t nb = 1u << c, words = (nb + 1) / 2;
+  const uint32_t t = threadIdx.x;
+  for (uint32_t k = t; k < words; k += kHistThreads) h[k] = 0u;
+  __syncthreads();
+  const uint64_t first = (uint64_t)blockIdx.x * per_group;
+  for (uint32_t k = t; k < per_group; k += kHistThreads) {
+    const uint64_t i = first + k;
+    if (i >= n) break;
+    const Fe s = scalar_plain(sc, i);
+    for (int w = 0; w < windows; ++w) {
+      const uint32_t d = digit(s, c, w);
+      const uint64_t e = (uint64_t)w * n + i;
+      digits[e] = (uint16_t)d;
+      if (d) {
+        const uint32_t sh = (d & 1u) * 16u;
+        ranks[e] = (uint16_t)(atomicAdd(&h[d >> 1], 1u << sh) >> sh);
+      }
+    }
   }
+  __syncthreads();
+  uint32_t* row = hist + (uint64_t)blockIdx.x * nb;
+  for (uint32_t d = t; d < nb; d += kHistThreads) row[d] = (h[d >> 1] >> ((d & 1u) * 16u)) & 0xFFFFu;
+}
+
+// Per bucket d: hist[g 2^c + d] <- the counts of d in groups before g, and
+// counts[d] = the total.
+__global__ void __launch_bounds__(256) column_scan_kernel(uint32_t* __restrict__ hist, uint32_t nb, uint32_t groups,
+                                                          uint32_t* __restrict__ counts) {
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nb) return;
+  uint32_t run = 0;
+  for (uint32_t g = 0; g < groups; ++g) {
+    const uint64_t k = (uint64_t)g * nb + d;
+    const uint32_t v = hist[k];
+    hist[k] = run;
+    run += v;
+  }
+  counts[d] = run;
 }
 
 // Exclusive scan of counts[0 .. nb) into offsets[0 .. nb] (offsets[nb] =
-// total).  One workgroup of 1024 threads, each summing a contiguous run.
-__global__ void __launch_bounds__(1024) scan_kernel(const uint32_t* __restrict__ counts, uint32_t nb,
-                                                    uint32_t* __restrict__ offsets) {
-  __shared__ uint32_t part[1024];
+// total), nb = 2^c <= 2^16.  One workgroup of 1024 threads; thread t keeps
+// the run [t per, t per + per) of counts in registers (per <= 64; 16-byte
+// loads and stores when per is a multiple of 4), and a tree over the runs'
+// sums in LDS gives each run its start.
+constexpr uint32_t kScanThreads = 1024, kScanPer = 64;
+
+__global__ void __launch_bounds__(kScanThreads) scan_kernel(const uint32_t* __restrict__ counts, uint32_t nb,
+                                                            uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t part[kScanThreads];
   const uint32_t t = threadIdx.x;
-  const uint32_t per = (nb + 1023) / 1024;
-  const uint32_t lo = t * per, hi = min(nb, lo + per);
+  const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
+  const uint32_t lo = t * per;
+  const bool vec = (per & 3u) == 0;
+  uint32_t v[kScanPer];
+#pragma unroll
+  for (uint32_t q = 0; q < kScanPer / 4; ++q) {
+    if (vec && 4 * q < per) {
+      const uint4 u = reinterpret_cast<const uint4*>(counts + lo)[q];
+      v[4 * q] = u.x, v[4 * q + 1] = u.y, v[4 * q + 2] = u.z, v[4 * q + 3] = u.w;
+    } else {
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t j = 4 * q + r;
+        v[j] = !vec && j < per && lo + j < nb ? counts[lo + j] : 0u;
+      }
+    }
+  }
   uint32_t s = 0;
-  for (uint32_t k = lo; k < hi; ++k) s += counts[k];
+#pragma unroll
+  for (uint32_t j = 0; j < kScanPer; ++j) s += j < per ? v[j] : 0u;
   part[t] = s;
   __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = t >= off ? part[t - off] : 0u;
+  for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t x = t >= off ? part[t - off] : 0u;
     __syncthreads();
-    part[t] += v;
+    part[t] += x;
     __syncthreads();
   }
   uint32_t run = part[t] - s;  // exclusive prefix of this run
-  for (uint32_t k = lo; k < hi; ++k) {
-    offsets[k] = run;
-    run += counts[k];
+#pragma unroll
+  for (uint32_t j = 0; j < kScanPer; ++j) {
+    const uint32_t x = v[j];
+    v[j] = run;
+    run += j < per ? x : 0u;
   }
-  if (t == 1023) offsets[nb] = part[1023];
+#pragma unroll
+  for (uint32_t q = 0; q < kScanPer / 4; ++q) {
+    if (vec && 4 * q < per) {
+      reinterpret_cast<uint4*>(offsets + lo)[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t j = 4 * q + r;
+        if (!vec && j < per && lo + j < nb) offsets[lo + j] = v[j];
+      }
+    }
+  }
+  if (t == kScanThreads - 1) offsets[nb] = part[kScanThreads - 1];
 }
 
-// entries[offsets[d] + rank] = w n + i for every nonzero digit d: one
-// thread per entry, no atomics.
+// entries[offsets[d] + (earlier groups' count of d) + rank] = w n + i for
+// every nonzero digit d: one thread per entry, no atomics.  Workgroup L takes
+// window L mod W of scalar block L / W, so that the workgroups in flight at
+// once read the histogram rows of a few groups, which stay in L2.
 __global__ void __launch_bounds__(256) scatter_kernel(const uint16_t* __restrict__ digits,
-                                                      const uint32_t* __restrict__ ranks, uint64_t count,
+                                                      const uint16_t* __restrict__ ranks, uint64_t n, int windows,
+                                                      uint32_t per_group, uint32_t nb,
+                                                      const uint32_t* __restrict__ hist,
                                                       const uint32_t* __restrict__ offsets,
                                                       uint32_t* __restrict__ entries) {
-  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
+  const uint32_t w = blockIdx.x % (uint32_t)windows, blk = blockIdx.x / (uint32_t)windows;
+  const uint64_t i = (uint64_t)blk * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t e = (uint64_t)w * n + i;
   const uint32_t d = digits[e];
-  if (d) entries[offsets[d] + ranks[e]] = (uint32_t)e;
+  if (d) entries[offsets[d] + hist[(i / per_group) * nb + d] + ranks[e]] = (uint32_t)e;
 }
 
 // ---------------------------------------------------------------------------
-// Bucket accumulation: lane (bucket d, slice s) adds the points of slice s of
-// bucket d; partial[d * S + s] = that sum (XYZZ).
+// Bucket accumulation, balanced over lanes.  The E sorted entries are cut
+// into runs of K = max(kmin, ceil(E / lanes)) consecutive positions, one run
+// per lane, whatever the bucket sizes: every lane does the same number of
+// mixed additions, and the grid is sized to the device's resident waves, so
+// that the accumulation is one round of equal lanes.  A run crosses bucket
+// boundaries: lane j keeps one accumulator per bucket segment of its run and
+// stores the segment containing the run's first position in head[j], the one
+// containing its last position (when it is another) in tail[j], and every
+// segment between them, a whole bucket, straight into buckets[d].
 
-__global__ void __launch_bounds__(128) accumulate_kernel(const uint32_t* __restrict__ table,
+__device__ __forceinline__ uint32_t lane_span(uint32_t E, uint32_t lanes, uint32_t kmin) {
+  return max(kmin, (uint32_t)(((uint64_t)E + lanes - 1) / lanes));
+}
+
+constexpr uint32_t kAccumulateThreads = 128;
+
+__global__ void __launch_bounds__(kAccumulateThreads) accumulate_kernel(const uint32_t* __restrict__ table,
                                                          const uint32_t* __restrict__ entries,
                                                          const uint32_t* __restrict__ offsets, uint32_t nb,
-                                                         uint32_t slices, uint32_t* __restrict__ partial) {
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint64_t)nb * slices) return;
-  const uint32_t d = (uint32_t)(g / slices), s = (uint32_t)(g % slices);
-  const uint32_t lo = offsets[d], hi = offsets[d + 1];
-  const uint32_t len = hi - lo;
-  const uint32_t a = lo + (uint32_t)((uint64_t)len * s / slices);
-  const uint32_t b = lo + (uint32_t)((uint64_t)len * (s + 1) / slices);
-  Xyzz acc = infinity();
-  for (uint32_t k = a; k < b; ++k) acc = add_mixed(acc, load_affine(table, entries[k]));
-  store_xyzz(partial, g, acc);
-}
-
-// ---------------------------------------------------------------------------
-// Reduction by bits.  Level 0: lane (b, t) sums, over buckets d of chunk t
-// (chunk = `chunk` consecutive bucket indices, 8: a lane adds at most 8
-// buckets, the chunk's all when bit b lies above the chunk's bits) with bit
-// b of d set, the S slices of those buckets; out[b * T + t].
-
-__global__ void __launch_bounds__(128) bits_level0_kernel(const uint32_t* __restrict__ partial, uint32_t nb,
-                                                          uint32_t slices, int c, uint32_t chunk,
-                                                          uint32_t* __restrict__ out) {
-  const uint32_t T = (nb + chunk - 1) / chunk;
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint64_t)c * T) return;
-  const uint32_t b = (uint32_t)(g / T), t = (uint32_t)(g % T);
-  Xyzz acc = infinity();
-  const uint32_t lo = t * chunk, hi = min(nb, lo + chunk);
-  for (uint32_t d = lo; d < hi; ++d) {
-    if (!((d >> b) & 1u)) continue;
-    for (uint32_t s = 0; s < slices; ++s) acc = add(acc, load_xyzz(partial, (uint64_t)d * slices + s));
+                                                         uint32_t lanes, uint32_t kmin, uint32_t* __restrict__ head,
+                                                         uint32_t* __restrict__ tail,
+                                                         uint32_t* __restrict__ buckets) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= lanes) return;
+  const uint32_t E = offsets[nb];
+  const uint32_t K = lane_span(E, lanes, kmin);
+  const uint64_t start = (uint64_t)j * K;
+  if (start >= E) return;
+  const uint32_t lo_pos = (uint32_t)start;
+  const uint32_t end = (uint32_t)min<uint64_t>(start + K, E);
+  // the bucket holding position lo_pos: offsets[cur] <= lo_pos < offsets[cur + 1]
+  uint32_t lo = 0, hi = nb;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= lo_pos) lo = mid; else hi = mid;
   }
-  store_xyzz(out, g, acc);
+  uint32_t cur = lo, next = offsets[cur + 1];
+  bool first = true;
+  Xyzz acc = infinity();
+  for (uint32_t k = lo_pos; k < end; ++k) {
+    if (k == next) {  // bucket cur ends before position k
+      if (first) store_xyzz(head, j, acc); else store_xyzz(buckets, cur, acc);
+      first = false;
+      acc = infinity();
+      do {
+        ++cur;
+        next = offsets[cur + 1];
+      } while (next <= k);  // skip empty buckets
+    }
+    acc = add_mixed(acc, load_affine(table, entries[k]));
+  }
+  if (first) store_xyzz(head, j, acc); else store_xyzz(tail, j, acc);
 }
 
-__global__ void __launch_bounds__(128) sum_level_kernel(const uint32_t* __restrict__ in, uint32_t groups,
-                                                        uint32_t len, uint32_t chunk, uint32_t* __restrict__ out) {
-  // `groups` groups of `len` partials each; out: groups x ceil(len / chunk)
-  const uint32_t T = (len + chunk - 1) / chunk;
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (uint64_t)groups * T) return;
-  const uint32_t grp = (uint32_t)(g / T), t = (uint32_t)(g % T);
-  Xyzz acc = infinity();
-  const uint32_t lo = t * chunk, hi = min(len, lo + chunk);
-  for (uint32_t k = lo; k < hi; ++k) acc = add(acc, load_xyzz(in, (uint64_t)grp * len + k));
-  store_xyzz(out, g, acc);
+// Bucket d from the lanes' segments: the segment in the lane holding its
+// first position (that lane's head or tail), plus the heads of the lanes
+// that start inside it.  A bucket that begins and ends strictly inside one
+// lane's run was stored by that lane; an empty bucket is infinity.
+__global__ void __launch_bounds__(128) combine_kernel(const uint32_t* __restrict__ offsets, uint32_t nb,
+                                                      uint32_t lanes, uint32_t kmin,
+                                                      const uint32_t* __restrict__ head,
+                                                      const uint32_t* __restrict__ tail,
+                                                      uint32_t* __restrict__ buckets) {
+  const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nb) return;
+  const uint32_t lo = offsets[d], hi = offsets[d + 1];
+  if (lo == hi) {
+    store_xyzz(buckets, d, infinity());
+    return;
+  }
+  const uint32_t E = offsets[nb];
+  const uint32_t K = lane_span(E, lanes, kmin);
+  const uint32_t jl = lo / K, jh = (hi - 1) / K;
+  const uint64_t run_end = min<uint64_t>((uint64_t)(jl + 1) * K, E);
+  Xyzz acc;
+  if (lo == jl * K) acc = load_xyzz(head, jl);
+  else if (hi >= run_end) acc = load_xyzz(tail, jl);
+  else return;
+  for (uint32_t j = jl + 1; j <= jh; ++j) acc = add(acc, load_xyzz(head, j));
+  store_xyzz(buckets, d, acc);
 }
 
 // Tree sum in LDS of the workgroup's points p[t] (t < blockDim.x, a power of
@@ -397,9 +513,48 @@ __device__ __forceinline__ Xyzz lds_tree_sum(const Xyzz& p, Xyzz* sh) {
   return sh[0];
 }
 
-// G_b for b = blockIdx.x: the sum of `len` partials of bit b, 512 lanes each
-// summing a strided share, then a tree (96 KiB of LDS).
-constexpr int kReduceThreads = 512;
+// ---------------------------------------------------------------------------
+// Reduction by bits.  Buckets are grouped in chunks of kChunk consecutive
+// indices.  For a bit b at or above the chunk's bits, bit b is the same for
+// every bucket of chunk t (it is bit b - 3 of t), so its share of G_b is the
+// whole chunk sum S_t or nothing: S_t is computed once, for all those bits.
+
+// S_t = the sum of the buckets of chunk t.
+__global__ void __launch_bounds__(128) chunk_sum_kernel(const uint32_t* __restrict__ buckets, uint32_t nb,
+                                                        uint32_t* __restrict__ sums) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (nb + kChunk - 1) / kChunk) return;
+  Xyzz acc = infinity();
+  for (uint32_t d = t * kChunk; d < min(nb, (t + 1) * kChunk); ++d) acc = add(acc, load_xyzz(buckets, d));
+  store_xyzz(sums, t, acc);
+}
+
+// Level 0: lane (b, t) holds chunk t's share of G_b: below the chunk's bits,
+// the sum of its buckets with bit b set (at most kChunk / 2 of them); above,
+// S_t or infinity.  A workgroup of kLevel0Lanes lanes of one bit sums them by
+// a tree: out[b * ceil(T / kLevel0Lanes) + blockIdx.x].
+__global__ void __launch_bounds__(kLevel0Lanes) bits_level0_kernel(const uint32_t* __restrict__ buckets,
+                                                                   const uint32_t* __restrict__ sums, uint32_t nb,
+                                                                   uint32_t* __restrict__ out) {
+  __shared__ Xyzz sh[kLevel0Lanes];
+  const uint32_t T = (nb + kChunk - 1) / kChunk;
+  const uint32_t b = blockIdx.y, t = blockIdx.x * kLevel0Lanes + threadIdx.x;
+  Xyzz acc = infinity();
+  if (t < T) {
+    if ((1u << b) < kChunk) {
+      for (uint32_t d = t * kChunk; d < min(nb, (t + 1) * kChunk); ++d)
+        if ((d >> b) & 1u) acc = add(acc, load_xyzz(buckets, d));
+    } else if (((t * kChunk) >> b) & 1u) {
+      acc = load_xyzz(sums, t);
+    }
+  }
+  const Xyzz total = lds_tree_sum(acc, sh);
+  if (threadIdx.x == 0) store_xyzz(out, (uint64_t)b * gridDim.x + blockIdx.x, total);
+}
+
+// G_b for b = blockIdx.x: the sum of the `len` level-0 results of bit b,
+// kReduceThreads lanes each summing a strided share, then a tree.
+constexpr int kReduceThreads = 128;
 __global__ void __launch_bounds__(kReduceThreads) reduce_bit_kernel(const uint32_t* __restrict__ in, uint32_t len,
                                                                     uint32_t* __restrict__ out) {
   __shared__ Xyzz sh[kReduceThreads];
@@ -424,11 +579,6 @@ __global__ void __launch_bounds__(16) final_kernel(const uint32_t* __restrict__ 
   if (threadIdx.x == 0) store_xyzz(res, 0, total);
 }
 
-__global__ void __launch_bounds__(256) zero_kernel(uint32_t* __restrict__ p, uint64_t words) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < words) p[i] = 0;
-}
-
 inline uint32_t blocks(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
 }  // namespace
@@ -441,40 +591,51 @@ hipError_t launch_precompute(const uint32_t* pts, uint64_t n, uint64_t first, ui
   return hipGetLastError();
 }
 
+hipError_t accumulate_lanes(uint32_t* lanes) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(accumulate_kernel),
+                                                     kAccumulateThreads, 0);
+  if (e != hipSuccess) return e;
+  *lanes = (uint32_t)std::max(1, cus * std::max(1, per_cu)) * kAccumulateThreads;
+  return hipSuccess;
+}
+
 hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
   const uint32_t nb = 1u << m.c;  // bucket 0 unused
   hipError_t e;
-  // counts
-  hipLaunchKernelGGL(zero_kernel, dim3(blocks(nb, 256)), dim3(256), 0, s, m.counts, (uint64_t)nb);
+  // counting sort: group histograms, their column prefixes, bucket offsets,
+  // then the scatter
+  hipLaunchKernelGGL(hist_kernel, dim3(m.groups), dim3(kHistThreads), 0, s, m.scalars, m.n, m.c, m.windows,
+                     m.per_group, m.digits, m.ranks, m.hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (m.n) {
-    hipLaunchKernelGGL(digits_kernel, dim3(blocks(m.n, 256)), dim3(256), 0, s, m.scalars, m.n, m.c, m.windows,
-                       m.digits, m.ranks, m.counts);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, m.counts, nb, m.offsets);
+  hipLaunchKernelGGL(column_scan_kernel, dim3(blocks(nb, 256)), dim3(256), 0, s, m.hist, nb, m.groups, m.counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (m.n) {
-    const uint64_t count = (uint64_t)m.windows * m.n;
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks(count, 256)), dim3(256), 0, s, m.digits, m.ranks, count, m.offsets,
-                       m.entries);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  const uint64_t lanes = (uint64_t)nb * m.slices;
-  hipLaunchKernelGGL(accumulate_kernel, dim3(blocks(lanes, 128)), dim3(128), 0, s, m.table, m.entries, m.offsets, nb,
-                     m.slices, m.partial);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, m.counts, nb, m.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // each bucket's slices into one point
-  hipLaunchKernelGGL(sum_level_kernel, dim3(blocks(nb, 128)), dim3(128), 0, s, m.partial, nb, m.slices, m.slices,
-                     m.buckets);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks(m.n, 256) * (uint32_t)m.windows), dim3(256), 0, s, m.digits,
+                     m.ranks, m.n, m.windows, m.per_group, nb, m.hist, m.offsets, m.entries);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // bucket sums: equal runs of sorted entries per lane, then the runs'
+  // boundary segments into their buckets
+  hipLaunchKernelGGL(accumulate_kernel, dim3(blocks(m.lanes, kAccumulateThreads)), dim3(kAccumulateThreads), 0, s,
+                     m.table, m.entries, m.offsets, nb, m.lanes, m.kmin, m.head, m.tail, m.buckets);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(combine_kernel, dim3(blocks(nb, 128)), dim3(128), 0, s, m.offsets, nb, m.lanes, m.kmin, m.head,
+                     m.tail, m.buckets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // reduction by bits
-  uint32_t T = (nb + m.chunk - 1) / m.chunk;
-  hipLaunchKernelGGL(bits_level0_kernel, dim3(blocks((uint64_t)m.c * T, 128)), dim3(128), 0, s, m.buckets, nb, 1u,
-                     m.c, m.chunk, m.level_a);
+  const uint32_t T = (nb + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(T, 128)), dim3(128), 0, s, m.buckets, nb, m.chunk_sums);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // each bit's partials into G_b, then sum_b 2^b G_b
-  hipLaunchKernelGGL(reduce_bit_kernel, dim3(m.c), dim3(kReduceThreads), 0, s, m.level_a, T, m.level_b);
+  const uint32_t T0 = blocks(T, kLevel0Lanes);  // level-0 results per bit
+  hipLaunchKernelGGL(bits_level0_kernel, dim3(T0, m.c), dim3(kLevel0Lanes), 0, s, m.buckets, m.chunk_sums, nb,
+                     m.level_a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // each bit's level-0 results into G_b, then sum_b 2^b G_b
+  hipLaunchKernelGGL(reduce_bit_kernel, dim3(m.c), dim3(kReduceThreads), 0, s, m.level_a, T0, m.level_b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(final_kernel, dim3(1), dim3(16), 0, s, m.level_b, m.c, m.result);
   return hipGetLastError();

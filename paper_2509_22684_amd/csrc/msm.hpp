@@ -8,6 +8,8 @@ namespace msm {
 
 constexpr int kPointWords = 24;  // affine point: x, y as 12 limbs each
 constexpr int kXyzzWords = 48;   // X, Y, ZZ, ZZZ
+constexpr uint32_t kChunk = 8;         // buckets per chunk in the reduction by bits
+constexpr uint32_t kLevel0Lanes = 64;  // level-0 lanes summed per result in the reduction by bits
 
 // Everything one MSM launch touches; the buffers are slices of the caller's
 // workspace (sizes in msm_workspace_bytes).
@@ -17,17 +19,22 @@ struct MsmLaunch {
   uint64_t n;
   int c;                    // window bits
   int windows;
-  uint32_t slices;          // lanes per bucket in the accumulation
-  uint32_t chunk;           // partials summed per lane in the reduction
+  uint32_t per_group;       // scalars per histogram group, per_group x windows <= 65535
+  uint32_t groups;          // ceil(n / per_group)
+  uint32_t lanes;           // accumulation lanes (accumulate_lanes)
+  uint32_t kmin;            // fewest sorted entries per lane
   uint16_t* digits;         // windows x n
+  uint16_t* ranks;          // windows x n: an entry's place among its group's entries of its bucket
+  uint32_t* hist;           // groups x 2^c
   uint32_t* counts;         // 2^c
   uint32_t* offsets;        // 2^c + 1
-  uint32_t* ranks;          // windows x n: an entry's place in its bucket
   uint32_t* entries;        // windows x n
-  uint32_t* partial;        // 2^c x slices XYZZ
+  uint32_t* head;           // lanes XYZZ
+  uint32_t* tail;           // lanes XYZZ
   uint32_t* buckets;        // 2^c XYZZ
-  uint32_t* level_a;        // c x ceil(2^c / chunk) XYZZ
-  uint32_t* level_b;        // same
+  uint32_t* chunk_sums;     // ceil(2^c / kChunk) XYZZ
+  uint32_t* level_a;        // c x ceil(ceil(2^c / kChunk) / kLevel0Lanes) XYZZ
+  uint32_t* level_b;        // c XYZZ
   uint32_t* result;         // one XYZZ point
 };
 
@@ -35,6 +42,8 @@ struct MsmLaunch {
 // scratch: count x windows x 60 words.
 hipError_t launch_precompute(const uint32_t* pts, uint64_t n, uint64_t first, uint64_t count, int c, int windows,
                              uint32_t* table, uint32_t* scratch, hipStream_t s);
+// Accumulation lanes that are resident on the current device at once.
+hipError_t accumulate_lanes(uint32_t* lanes);
 hipError_t launch_msm(const MsmLaunch& m, hipStream_t s);
 
 }  // namespace msm

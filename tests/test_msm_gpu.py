@@ -96,6 +96,36 @@ def test_msm_structured_bases_closed_form(cuda, multiples_g, n):
         assert got == M.msm_buckets(scal, mults[:n], 8)
 
 
+def _repeated_digit_scalar(c, d):
+    """The scalar whose c-bit windows all hold d (below 2^255), reduced mod r."""
+    v = 0
+    for w in range((255 + c - 1) // c):
+        v |= d << (c * w)
+    return (v & ((1 << 255) - 1)) % FR.p
+
+
+@pytest.mark.parametrize("window_bits", [0, 16])
+@pytest.mark.parametrize("mix", ["all_equal", "half_equal", "mostly_zero"])
+def test_msm_skewed_buckets_closed_form(cuda, multiples_g, mix, window_bits):
+    """Bucket sizes far from uniform: one bucket holding most entries (its
+    sum spans thousands of accumulation lanes), many buckets inside one
+    lane's run, and mostly empty buckets."""
+    G, mults = multiples_g
+    n = 1 << 14
+    rng = random.Random(f"{mix}-{window_bits}")
+    c = window_bits or 12
+    rep = _repeated_digit_scalar(c, 5)
+    if mix == "all_equal":
+        scal = [rep] * n
+    elif mix == "half_equal":
+        scal = [rep if k % 2 else rng.randrange(FR.p) for k in range(n)]
+    else:
+        scal = [rng.randrange(FR.p) if k % 10 == 0 else 0 for k in range(n)]
+    got, bases = _run(mults[:n], scal, cuda, window_bits)
+    assert bases.window_bits == c
+    assert got == M.mul(sum(s * (i + 1) for i, s in enumerate(scal)) % FR.p, G)
+
+
 def test_msm_scalars_from_the_quotient(cuda, multiples_g):
     """The quotient chain's output H (Montgomery Fr limbs) feeds the MSM
     directly, as in a Groth16 prover's H-query."""
