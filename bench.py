@@ -186,11 +186,13 @@ def small_configs_leg(dev) -> dict:
     return out
 
 
-def batch_leg(dev, reps: int = 20) -> dict:
+def batch_leg(dev, reps: int = 50, warm: int = 100) -> dict:
     """64 forward NTTs (log2 n uniform in [10, 18], 48 BLS12-381 + 16 BN254):
     jobs/s for one launch sequence per NTT (each size on its tuned stand-alone
     schedule) versus one batch (tuned batchable schedules) replayed from its
-    graph or launched directly."""
+    graph or launched directly.  Each way is timed in steady state, after
+    `warm` untimed repetitions: the first few dozen replays in a process run
+    up to 15% slower while the GPU's clocks rise under the new load."""
     import numpy as np
     import torch
 
@@ -221,7 +223,7 @@ def batch_leg(dev, reps: int = 20) -> dict:
     batch = Batch(job_plans, bufs)
 
     def timed(fn):
-        for _ in range(3):
+        for _ in range(warm):
             fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -256,6 +258,7 @@ def batch_leg(dev, reps: int = 20) -> dict:
                           "workgroups": batch.grid},
         "batched_direct": {"ms": t_eager, "jobs_per_s": len(jobs) / (t_eager * 1e-3)},
         "batched_over_per_launch": t_per / t_graph,
+        "warmup_repetitions": warm, "timed_repetitions": reps,
         "status": status,
     }
 
