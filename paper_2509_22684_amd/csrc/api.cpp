@@ -1626,7 +1626,8 @@ namespace {
 constexpr int kScalarBits = 255;  // BLS12-381 Fr elements are below 2^255
 
 struct MsmLayout {
-  size_t digits, ranks, hist, counts, offsets, entries, head, tail, buckets, chunk_sums, level_a, level_b, total;
+  size_t digits, ranks, hist, counts, offsets, entries, head, tail, big, big_count, buckets, chunk_sums, level_a,
+      level_b, total;
 };
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
@@ -1655,6 +1656,10 @@ MsmLayout msm_layout(const msm_bases* b) {
   off += round256((size_t)b->lanes * xyzz);
   L.tail = off;
   off += round256((size_t)b->lanes * xyzz);
+  L.big = off;
+  off += round256((size_t)zk::msm::max_big_buckets(b->lanes) * sizeof(uint32_t));
+  L.big_count = off;
+  off += round256(sizeof(uint32_t));
   L.buckets = off;
   off += round256(nb * xyzz);
   L.chunk_sums = off;
@@ -1785,6 +1790,8 @@ int msm_compute(const msm_bases* b, const void* d_scalars, void* d_result, void*
   m.entries = reinterpret_cast<uint32_t*>(w + L.entries);
   m.head = reinterpret_cast<uint32_t*>(w + L.head);
   m.tail = reinterpret_cast<uint32_t*>(w + L.tail);
+  m.big = reinterpret_cast<uint32_t*>(w + L.big);
+  m.big_count = reinterpret_cast<uint32_t*>(w + L.big_count);
   m.buckets = reinterpret_cast<uint32_t*>(w + L.buckets);
   m.chunk_sums = reinterpret_cast<uint32_t*>(w + L.chunk_sums);
   m.level_a = reinterpret_cast<uint32_t*>(w + L.level_a);

@@ -345,7 +345,8 @@ __global__ void __launch_bounds__(256) column_scan_kernel(uint32_t* __restrict__
 constexpr uint32_t kScanThreads = 1024, kScanPer = 64;
 
 __global__ void __launch_bounds__(kScanThreads) scan_kernel(const uint32_t* __restrict__ counts, uint32_t nb,
-                                                            uint32_t* __restrict__ offsets) {
+                                                            uint32_t* __restrict__ offsets,
+                                                            uint32_t* __restrict__ big_count) {
   __shared__ uint32_t part[kScanThreads];
   const uint32_t t = threadIdx.x;
   const uint32_t per = (nb + kScanThreads - 1) / kScanThreads;
@@ -396,6 +397,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_kernel(const uint32_t* __re
     }
   }
   if (t == kScanThreads - 1) offsets[nb] = part[kScanThreads - 1];
+  if (t == 0) *big_count = 0u;  // the combine step's list of large buckets starts empty
 }
 
 // entries[offsets[d] + (earlier groups' count of d) + rank] = w n + i for
@@ -474,12 +476,17 @@ __global__ void __launch_bounds__(kAccumulateThreads) accumulate_kernel(const ui
 // Bucket d from the lanes' segments: the segment in the lane holding its
 // first position (that lane's head or tail), plus the heads of the lanes
 // that start inside it.  A bucket that begins and ends strictly inside one
-// lane's run was stored by that lane; an empty bucket is infinity.
+// lane's run was stored by that lane; an empty bucket is infinity.  A bucket
+// spanning more than kCombineSerial runs (skewed scalars: many equal
+// digits) is listed in big[] for big_combine_kernel instead of being summed
+// by one lane.
+
 __global__ void __launch_bounds__(128) combine_kernel(const uint32_t* __restrict__ offsets, uint32_t nb,
                                                       uint32_t lanes, uint32_t kmin,
                                                       const uint32_t* __restrict__ head,
                                                       const uint32_t* __restrict__ tail,
-                                                      uint32_t* __restrict__ buckets) {
+                                                      uint32_t* __restrict__ buckets, uint32_t* __restrict__ big,
+                                                      uint32_t* __restrict__ big_count) {
   const uint32_t d = blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= nb) return;
   const uint32_t lo = offsets[d], hi = offsets[d + 1];
@@ -490,6 +497,10 @@ __global__ void __launch_bounds__(128) combine_kernel(const uint32_t* __restrict
   const uint32_t E = offsets[nb];
   const uint32_t K = lane_span(E, lanes, kmin);
   const uint32_t jl = lo / K, jh = (hi - 1) / K;
+  if (jh - jl > kCombineSerial) {
+    big[atomicAdd(big_count, 1u)] = d;
+    return;
+  }
   const uint64_t run_end = min<uint64_t>((uint64_t)(jl + 1) * K, E);
   Xyzz acc;
   if (lo == jl * K) acc = load_xyzz(head, jl);
@@ -511,6 +522,34 @@ __device__ __forceinline__ Xyzz lds_tree_sum(const Xyzz& p, Xyzz* sh) {
     __syncthreads();
   }
   return sh[0];
+}
+
+// A listed bucket (workgroup b takes big[b] while b < *big_count): its
+// first segment (it spans more than one run, so that is the head or the
+// tail of its first lane) and the heads of the runs inside it, summed by
+// kBigThreads lanes with strided shares and a tree.  At most
+// lanes / kCombineSerial + 1 buckets can be listed.
+constexpr int kBigThreads = 256;
+
+__global__ void __launch_bounds__(kBigThreads) big_combine_kernel(const uint32_t* __restrict__ offsets, uint32_t nb,
+                                                                  uint32_t lanes, uint32_t kmin,
+                                                                  const uint32_t* __restrict__ head,
+                                                                  const uint32_t* __restrict__ tail,
+                                                                  const uint32_t* __restrict__ big,
+                                                                  const uint32_t* __restrict__ big_count,
+                                                                  uint32_t* __restrict__ buckets) {
+  __shared__ Xyzz sh[kBigThreads];
+  if (blockIdx.x >= *big_count) return;  // the same for every thread of the workgroup
+  const uint32_t d = big[blockIdx.x];
+  const uint32_t lo = offsets[d], hi = offsets[d + 1];
+  const uint32_t E = offsets[nb];
+  const uint32_t K = lane_span(E, lanes, kmin);
+  const uint32_t jl = lo / K, jh = (hi - 1) / K;
+  Xyzz acc = infinity();
+  if (threadIdx.x == 0) acc = lo == jl * K ? load_xyzz(head, jl) : load_xyzz(tail, jl);
+  for (uint32_t j = jl + 1 + threadIdx.x; j <= jh; j += kBigThreads) acc = add(acc, load_xyzz(head, j));
+  const Xyzz total = lds_tree_sum(acc, sh);
+  if (threadIdx.x == 0) store_xyzz(buckets, d, total);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +652,7 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(column_scan_kernel, dim3(blocks(nb, 256)), dim3(256), 0, s, m.hist, nb, m.groups, m.counts);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, m.counts, nb, m.offsets);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, m.counts, nb, m.offsets, m.big_count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(scatter_kernel, dim3(blocks(m.n, 256) * (uint32_t)m.windows), dim3(256), 0, s, m.digits,
                      m.ranks, m.n, m.windows, m.per_group, nb, m.hist, m.offsets, m.entries);
@@ -624,7 +663,10 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
                      m.table, m.entries, m.offsets, nb, m.lanes, m.kmin, m.head, m.tail, m.buckets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(combine_kernel, dim3(blocks(nb, 128)), dim3(128), 0, s, m.offsets, nb, m.lanes, m.kmin, m.head,
-                     m.tail, m.buckets);
+                     m.tail, m.buckets, m.big, m.big_count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(big_combine_kernel, dim3(max_big_buckets(m.lanes)), dim3(kBigThreads), 0, s, m.offsets, nb,
+                     m.lanes, m.kmin, m.head, m.tail, m.big, m.big_count, m.buckets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // reduction by bits
   const uint32_t T = (nb + kChunk - 1) / kChunk;

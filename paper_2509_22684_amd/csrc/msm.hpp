@@ -31,6 +31,8 @@ struct MsmLaunch {
   uint32_t* entries;        // windows x n
   uint32_t* head;           // lanes XYZZ
   uint32_t* tail;           // lanes XYZZ
+  uint32_t* big;            // max_big_buckets(lanes) bucket indices
+  uint32_t* big_count;      // one word
   uint32_t* buckets;        // 2^c XYZZ
   uint32_t* chunk_sums;     // ceil(2^c / kChunk) XYZZ
   uint32_t* level_a;        // c x ceil(ceil(2^c / kChunk) / kLevel0Lanes) XYZZ
@@ -42,6 +44,12 @@ struct MsmLaunch {
 // scratch: count x windows x 60 words.
 hipError_t launch_precompute(const uint32_t* pts, uint64_t n, uint64_t first, uint64_t count, int c, int windows,
                              uint32_t* table, uint32_t* scratch, hipStream_t s);
+// A combine lane adds at most kCombineSerial runs' heads; a bucket spanning
+// more runs is listed for a workgroup.  Such buckets own more than
+// kCombineSerial run starts each, so at most lanes / kCombineSerial + 1.
+constexpr uint32_t kCombineSerial = 16;
+inline uint32_t max_big_buckets(uint32_t lanes) { return lanes / kCombineSerial + 1u; }
+
 // Accumulation lanes that are resident on the current device at once.
 hipError_t accumulate_lanes(uint32_t* lanes);
 hipError_t launch_msm(const MsmLaunch& m, hipStream_t s);

@@ -105,11 +105,12 @@ def _repeated_digit_scalar(c, d):
 
 
 @pytest.mark.parametrize("window_bits", [0, 16])
-@pytest.mark.parametrize("mix", ["all_equal", "half_equal", "mostly_zero"])
+@pytest.mark.parametrize("mix", ["all_equal", "half_equal", "mostly_zero", "zero_one"])
 def test_msm_skewed_buckets_closed_form(cuda, multiples_g, mix, window_bits):
     """Bucket sizes far from uniform: one bucket holding most entries (its
-    sum spans thousands of accumulation lanes), many buckets inside one
-    lane's run, and mostly empty buckets."""
+    sum spans thousands of accumulation lanes and goes to the workgroup
+    combine), many buckets inside one lane's run, mostly empty buckets, and
+    witness-like scalars that are mostly 0 or 1 (bucket 1 of window 0)."""
     G, mults = multiples_g
     n = 1 << 14
     rng = random.Random(f"{mix}-{window_bits}")
@@ -119,8 +120,10 @@ def test_msm_skewed_buckets_closed_form(cuda, multiples_g, mix, window_bits):
         scal = [rep] * n
     elif mix == "half_equal":
         scal = [rep if k % 2 else rng.randrange(FR.p) for k in range(n)]
-    else:
+    elif mix == "mostly_zero":
         scal = [rng.randrange(FR.p) if k % 10 == 0 else 0 for k in range(n)]
+    else:
+        scal = [rng.randrange(FR.p) if k % 50 == 0 else k % 2 for k in range(n)]
     got, bases = _run(mults[:n], scal, cuda, window_bits)
     assert bases.window_bits == c
     assert got == M.mul(sum(s * (i + 1) for i, s in enumerate(scal)) % FR.p, G)
@@ -140,6 +143,17 @@ def test_msm_scalars_from_the_quotient(cuda, multiples_g):
     bases = MsmBases(to_dev(M.points_to_device_layout(mults[:n]), cuda))
     got = _result_point(bases.msm(H))
     assert got == M.mul(sum(v * (i + 1) for i, v in enumerate(h)) % FR.p, G)
+
+
+def test_msm_one_bucket_2_16(cuda, multiples_g):
+    """2^16 equal scalars with every window digit equal: one bucket of about
+    1.2 M entries, summed by the workgroup combine over its runs' heads."""
+    G, mults = multiples_g
+    n = 1 << 16
+    rep = _repeated_digit_scalar(14, 9)
+    got, bases = _run(mults, [rep] * n, cuda)
+    assert bases.window_bits == 14
+    assert got == M.mul(rep * (n * (n + 1) // 2) % FR.p, G)
 
 
 @pytest.mark.slow
