@@ -1637,7 +1637,8 @@ MsmLayout msm_layout(const msm_bases* b) {
   const size_t nb = size_t(1) << b->c;
   const size_t entries = (size_t)b->windows * b->n;
   const size_t T = (nb + zk::msm::kChunk - 1) / zk::msm::kChunk;
-  const size_t T0 = (T + zk::msm::kLevel0Lanes - 1) / zk::msm::kLevel0Lanes;
+  const size_t per = (size_t)zk::msm::kLevel0Lanes * zk::msm::kLevel0Chunks;
+  const size_t T0 = (T + per - 1) / per;
   const size_t xyzz = zk::msm::kXyzzWords * sizeof(uint32_t);
   size_t off = 0;
   L.digits = off;

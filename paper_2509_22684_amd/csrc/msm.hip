@@ -568,23 +568,26 @@ __global__ void __launch_bounds__(128) chunk_sum_kernel(const uint32_t* __restri
   store_xyzz(sums, t, acc);
 }
 
-// Level 0: lane (b, t) holds chunk t's share of G_b: below the chunk's bits,
-// the sum of its buckets with bit b set (at most kChunk / 2 of them); above,
-// S_t or infinity.  A workgroup of kLevel0Lanes lanes of one bit sums them by
-// a tree: out[b * ceil(T / kLevel0Lanes) + blockIdx.x].
+// Level 0: lane (b, u) holds the share of G_b of chunks t = u C .. u C + C - 1
+// (C = kLevel0Chunks): below the chunks' bits, the sum of their buckets with
+// bit b set (at most kChunk / 2 per chunk); above, the sums S_t of the
+// chunks with bit b set.  A workgroup of kLevel0Lanes lanes of one bit sums
+// them by a tree: out[b * ceil(T / (kLevel0Lanes C)) + blockIdx.x].  Two
+// chunks per lane keep one wave per SIMD, where a point addition's latency
+// is shortest.
 __global__ void __launch_bounds__(kLevel0Lanes) bits_level0_kernel(const uint32_t* __restrict__ buckets,
                                                                    const uint32_t* __restrict__ sums, uint32_t nb,
                                                                    uint32_t* __restrict__ out) {
   __shared__ Xyzz sh[kLevel0Lanes];
   const uint32_t T = (nb + kChunk - 1) / kChunk;
-  const uint32_t b = blockIdx.y, t = blockIdx.x * kLevel0Lanes + threadIdx.x;
+  const uint32_t b = blockIdx.y, u = blockIdx.x * kLevel0Lanes + threadIdx.x;
   Xyzz acc = infinity();
-  if (t < T) {
+  for (uint32_t t = u * kLevel0Chunks; t < min(T, (u + 1) * kLevel0Chunks); ++t) {
     if ((1u << b) < kChunk) {
       for (uint32_t d = t * kChunk; d < min(nb, (t + 1) * kChunk); ++d)
         if ((d >> b) & 1u) acc = add(acc, load_xyzz(buckets, d));
     } else if (((t * kChunk) >> b) & 1u) {
-      acc = load_xyzz(sums, t);
+      acc = add(acc, load_xyzz(sums, t));
     }
   }
   const Xyzz total = lds_tree_sum(acc, sh);
@@ -672,7 +675,7 @@ hipError_t launch_msm(const MsmLaunch& m, hipStream_t s) {
   const uint32_t T = (nb + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(chunk_sum_kernel, dim3(blocks(T, 128)), dim3(128), 0, s, m.buckets, nb, m.chunk_sums);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const uint32_t T0 = blocks(T, kLevel0Lanes);  // level-0 results per bit
+  const uint32_t T0 = blocks(T, kLevel0Lanes * kLevel0Chunks);  // level-0 results per bit
   hipLaunchKernelGGL(bits_level0_kernel, dim3(T0, m.c), dim3(kLevel0Lanes), 0, s, m.buckets, m.chunk_sums, nb,
                      m.level_a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

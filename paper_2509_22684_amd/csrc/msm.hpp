@@ -10,6 +10,7 @@ constexpr int kPointWords = 24;  // affine point: x, y as 12 limbs each
 constexpr int kXyzzWords = 48;   // X, Y, ZZ, ZZZ
 constexpr uint32_t kChunk = 8;         // buckets per chunk in the reduction by bits
 constexpr uint32_t kLevel0Lanes = 64;  // level-0 lanes summed per result in the reduction by bits
+constexpr uint32_t kLevel0Chunks = 2;  // chunks per level-0 lane
 
 // Everything one MSM launch touches; the buffers are slices of the caller's
 // workspace (sizes in msm_workspace_bytes).
@@ -35,7 +36,7 @@ struct MsmLaunch {
   uint32_t* big_count;      // one word
   uint32_t* buckets;        // 2^c XYZZ
   uint32_t* chunk_sums;     // ceil(2^c / kChunk) XYZZ
-  uint32_t* level_a;        // c x ceil(ceil(2^c / kChunk) / kLevel0Lanes) XYZZ
+  uint32_t* level_a;        // c x ceil(ceil(2^c / kChunk) / (kLevel0Lanes kLevel0Chunks)) XYZZ
   uint32_t* level_b;        // c XYZZ
   uint32_t* result;         // one XYZZ point
 };
