@@ -1,7 +1,11 @@
 // The base field of BLS12-381 G1, F_q (381-bit q), for the MSM kernels.
 //
 // An element is twelve 32-bit limbs, little-endian, in Montgomery form with
-// R = 2^384, canonical in [0, q).  FF_mul is the same finely integrated
+// R = 2^384.  Inside the kernels elements are kept in [0, 2q) (lazy
+// reduction: 4q < 2^384, so a Montgomery product of two such elements is
+// below 2q without a final subtraction, and sums and differences reduce
+// modulo 2q); canon() brings one to [0, q) where it leaves the device.
+// FF_mul is the same finely integrated
 // product scanning as the scalar fields' (field.hpp): each 32x32-bit
 // partial product is one v_mad_u64_u32 into a 64-bit column accumulator
 // whose carry-out feeds a v_addc_co_u32 column counter, 2 N^2 = 288 of each
@@ -20,6 +24,8 @@ constexpr int kN = 12;
 // q = (x0 - 1)^2 (x0^4 - x0^2 + 1) / 3 + x0, x0 = -0xd201000000010000.
 constexpr uint32_t kQ[kN] = {0xffffaaabu, 0xb9feffffu, 0xb153ffffu, 0x1eabfffeu, 0xf6b0f624u, 0x6730d2a0u,
                              0xf38512bfu, 0x64774b84u, 0x434bacd7u, 0x4b1ba7b6u, 0x397fe69au, 0x1a0111eau};
+constexpr uint32_t k2Q[kN] = {0xffff5556u, 0x73fdffffu, 0x62a7ffffu, 0x3d57fffdu, 0xed61ec48u, 0xce61a541u,
+                              0xe70a257eu, 0xc8ee9709u, 0x869759aeu, 0x96374f6cu, 0x72ffcd34u, 0x340223d4u};
 constexpr uint32_t kInv = 0xfffcfffdu;  // -q^-1 mod 2^32
 // 2^384 mod q: the Montgomery form of 1.
 constexpr uint32_t kOne[kN] = {0x0002fffdu, 0x76090000u, 0xc40c0002u, 0xebf4000bu, 0x53c758bau, 0x5f489857u,
@@ -43,34 +49,42 @@ __device__ __forceinline__ Fq one() {
   return r;
 }
 
+// a = 0 mod q, for a in [0, 2q): a is 0 or q.
 __device__ __forceinline__ bool is_zero(const Fq& a) {
-  uint32_t o = 0;
+  uint32_t o = 0, oq = 0;
 #pragma unroll
-  for (int j = 0; j < kN; ++j) o |= a.v[j];
-  return o == 0;
+  for (int j = 0; j < kN; ++j) {
+    o |= a.v[j];
+    oq |= a.v[j] ^ kQ[j];
+  }
+  return o == 0 || oq == 0;
 }
 
-__device__ __forceinline__ bool equal(const Fq& a, const Fq& b) {
-  uint32_t o = 0;
+// a in [0, 2q) to [0, q).
+__device__ __forceinline__ Fq canon(const Fq& a) {
+  Fq d;
+  unsigned int br = 0;
 #pragma unroll
-  for (int j = 0; j < kN; ++j) o |= a.v[j] ^ b.v[j];
-  return o == 0;
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(a.v[j], kQ[j], br, &br);
+#pragma unroll
+  for (int j = 0; j < kN; ++j) d.v[j] = br ? a.v[j] : d.v[j];
+  return d;
 }
 
-// a + b mod q (a, b canonical; a + b < 2q < 2^384).
+// a + b mod 2q (a, b in [0, 2q); a + b < 4q < 2^384).
 __device__ __forceinline__ Fq add(const Fq& a, const Fq& b) {
   Fq s, d;
   unsigned int c = 0, br = 0;
 #pragma unroll
   for (int j = 0; j < kN; ++j) s.v[j] = __builtin_addc(a.v[j], b.v[j], c, &c);
 #pragma unroll
-  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(s.v[j], kQ[j], br, &br);
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(s.v[j], k2Q[j], br, &br);
 #pragma unroll
   for (int j = 0; j < kN; ++j) d.v[j] = br ? s.v[j] : d.v[j];
   return d;
 }
 
-// a - b mod q.
+// a - b mod 2q (a, b in [0, 2q)).
 __device__ __forceinline__ Fq sub(const Fq& a, const Fq& b) {
   Fq d;
   unsigned int br = 0, c = 0;
@@ -78,7 +92,7 @@ __device__ __forceinline__ Fq sub(const Fq& a, const Fq& b) {
   for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(a.v[j], b.v[j], br, &br);
   const uint32_t mask = 0u - br;
 #pragma unroll
-  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_addc(d.v[j], kQ[j] & mask, c, &c);
+  for (int j = 0; j < kN; ++j) d.v[j] = __builtin_addc(d.v[j], k2Q[j] & mask, c, &c);
   return d;
 }
 
@@ -151,16 +165,11 @@ __device__ __forceinline__ void mul_k(Fq* r, const Fq* a, const Fq* b) {
     }
   }
 #undef ZK_FQ_TERMS
-  // t < 2q: one conditional subtraction
+  // t < 2q for a, b < 2q: left there (lazy reduction)
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    Fq d;
-    unsigned int br = 0;
+  for (int k = 0; k < K; ++k)
 #pragma unroll
-    for (int j = 0; j < kN; ++j) d.v[j] = __builtin_subc(t[k][j], kQ[j], br, &br);
-#pragma unroll
-    for (int j = 0; j < kN; ++j) r[k].v[j] = br ? t[k][j] : d.v[j];
-  }
+    for (int j = 0; j < kN; ++j) r[k].v[j] = t[k][j];
 }
 #else
 // Host compilation pass: device code is parsed but never emitted here.

@@ -617,8 +617,15 @@ __global__ void __launch_bounds__(16) final_kernel(const uint32_t* __restrict__ 
     p = load_xyzz(G, (uint64_t)b);
     for (int k = 0; k < b; ++k) p = dbl(p);
   }
-  const Xyzz total = lds_tree_sum(p, sh);
-  if (threadIdx.x == 0) store_xyzz(res, 0, total);
+  Xyzz total = lds_tree_sum(p, sh);
+  if (threadIdx.x == 0) {
+    // the result leaves the device canonical
+    total.X = fq::canon(total.X);
+    total.Y = fq::canon(total.Y);
+    total.ZZ = fq::canon(total.ZZ);
+    total.ZZZ = fq::canon(total.ZZZ);
+    store_xyzz(res, 0, total);
+  }
 }
 
 inline uint32_t blocks(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
