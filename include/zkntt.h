@@ -279,22 +279,31 @@ typedef struct {
 #define ZK_BATCH_QUEUES_MASK (0x3f << ZK_BATCH_QUEUES_SHIFT)
 #define ZK_BATCH_QUEUES(q) ((int)(q) << ZK_BATCH_QUEUES_SHIFT)
 
+/* Without ZK_BATCH_GRAPH the call does not wait for the device: the work
+ * list stays in pinned host memory and is uploaded on the stream of the
+ * first ntt_batch_launch_eager.  With it, the work list is uploaded and the
+ * graph captured before the call returns. */
 int ntt_batch_create_jobs(ntt_batch **out, const ntt_batch_job *jobs, int njobs, int flags);
 
 /* Replay the batch's graph on `stream`: one persistent launch runs all jobs. */
 int ntt_batch_launch(const ntt_batch *b, void *stream);
 
-/* The same two kernels launched directly on `stream`, without the graph. */
+/* The same two kernels launched directly on `stream`, without the graph
+ * (after the work list's upload on its first call; each call also copies
+ * the batch's error word to host memory on `stream`). */
 int ntt_batch_launch_eager(const ntt_batch *b, void *stream);
 
 /* After the stream of the last launch has been synchronised: ZK_OK, or
  * ZK_EDEVICE if a dependency wait exceeded its poll limit (the kernel then
  * stops early) or the launch ended with items not run; the outputs are then
- * invalid. */
+ * invalid.  After an eager launch this reads host memory only; after a graph
+ * launch it copies the error word synchronously. */
 int ntt_batch_status(const ntt_batch *b);
 
 /* Poll limit of one dependency wait (default 2^22).  0 makes every
- * dependency wait fail at once (a test hook for the error path).  Synchronous. */
+ * dependency wait fail at once (a test hook for the error path).  Synchronous
+ * once the work list is on the device; before an eager batch's first launch
+ * it only updates the pending host copy. */
 int ntt_batch_set_spin_limit(ntt_batch *b, uint32_t polls);
 
 /* Work items (tiles) the persistent kernel drains (jobs run as grouped or

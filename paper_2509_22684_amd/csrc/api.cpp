@@ -902,6 +902,16 @@ struct ntt_batch {
   uint32_t grid = 0;
   void* d_mem = nullptr;  // descriptor block from the pool
   size_t d_mem_bytes = 0;
+  // Batches without a graph keep their descriptor image in the block's pinned
+  // host twin and upload it on the stream of their first launch, so that
+  // creating one never waits for the device; each of their launches also
+  // copies the error word back to the twin (status_host) on the launch
+  // stream.  The uploaded bytes; upload still to do; status in the twin.
+  void* h_mem = nullptr;
+  size_t upload_bytes = 0;
+  mutable bool upload_pending = false;
+  mutable bool status_on_host = false;
+  uint32_t* status_host = nullptr;
   hipEvent_t done_ev = nullptr;  // recorded on the launch stream after every launch
   bool launched = false;
   zk::BatchJob* d_jobs = nullptr;
@@ -1008,6 +1018,7 @@ struct DescPool {
     size_t bytes;
     void* ptr;
     hipEvent_t last_use;  // recorded after the last launch of the batch that held it, or null
+    void* host;           // pinned host twin of the same size, made on first need, or null
   };
   std::vector<Block> free_blocks;
 };
@@ -1022,7 +1033,7 @@ size_t desc_block_bytes(size_t need) {
   return b;
 }
 
-hipError_t take_desc(int dev, size_t need, void** out, size_t* got) {
+hipError_t take_desc(int dev, size_t need, void** out, size_t* got, void** host) {
   DescPool& dp = desc_pool();
   const size_t want = desc_block_bytes(need);
   {
@@ -1038,6 +1049,7 @@ hipError_t take_desc(int dev, size_t need, void** out, size_t* got) {
       dp.free_blocks.erase(dp.free_blocks.begin() + (long)best);
       *out = bl.ptr;
       *got = bl.bytes;
+      *host = bl.host;
       hipError_t e = hipSuccess;
       if (bl.last_use) {
         // the batch that held the block may still run if it was destroyed
@@ -1049,14 +1061,15 @@ hipError_t take_desc(int dev, size_t need, void** out, size_t* got) {
     }
   }
   *got = want;
+  *host = nullptr;
   return hipMalloc(out, want);
 }
 
-void give_desc(int dev, size_t bytes, void* ptr, hipEvent_t last_use) {
+void give_desc(int dev, size_t bytes, void* ptr, hipEvent_t last_use, void* host) {
   if (!ptr) return;
   DescPool& dp = desc_pool();
   std::lock_guard<std::mutex> lock(dp.mu);
-  dp.free_blocks.push_back(DescPool::Block{dev, bytes, ptr, last_use});
+  dp.free_blocks.push_back(DescPool::Block{dev, bytes, ptr, last_use, host});
 }
 
 void free_batch(ntt_batch* b) {
@@ -1067,7 +1080,7 @@ void free_batch(ntt_batch* b) {
   std::vector<hipEvent_t> evs(b->joins);
   evs.push_back(b->fork_ev);
   give_back(b->device, b->sides, evs);
-  give_desc(b->device, b->d_mem_bytes, b->d_mem, b->launched ? b->done_ev : nullptr);
+  give_desc(b->device, b->d_mem_bytes, b->d_mem, b->launched ? b->done_ev : nullptr, b->h_mem);
   if (!b->launched && b->done_ev) give_back(b->device, {}, {b->done_ev});
   delete b;
 }
@@ -1077,6 +1090,13 @@ void free_batch(ntt_batch* b) {
 // before and joined into s after, so that they all run at the same time
 // (the persistent grid then leaves room for the pass kernels).
 int batch_enqueue(const ntt_batch* b, hipStream_t s) {
+  if (b->upload_pending) {
+    // ordered before everything below on s, and through the fork on the
+    // side streams
+    hipError_t e = hipMemcpyAsync(b->d_mem, b->h_mem, b->upload_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+    b->upload_pending = false;
+  }
   if (!b->sides.empty()) {
     hipError_t e = hipEventRecord(b->fork_ev, s);
     for (hipStream_t x : b->sides)
@@ -1434,8 +1454,10 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   const size_t queues_bytes = ((sizeof(zk::BatchQueue) * queues.size() + 255) / 256) * 256;
   const size_t ctl_words = zk::kCtlDone + (size_t)njobs * zk::kMaxBatchPasses;
   const size_t ctl_bytes = ((ctl_words * sizeof(uint32_t) + 255) / 256) * 256;
-  e = take_desc(dev, jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t),
-                &b->d_mem, &b->d_mem_bytes);
+  // (the 256-byte-aligned word past the descriptors holds the status in the
+  // host twin)
+  e = take_desc(dev, jobs_bytes + items_bytes + queues_bytes + ctl_bytes + ptrs.size() * sizeof(uintptr_t) + 512,
+                &b->d_mem, &b->d_mem_bytes, &b->h_mem);
   if (e != hipSuccess) {
     b->d_mem = nullptr;
     free_batch(b);
@@ -1469,7 +1491,21 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   if (!ptrs.empty())
     std::memcpy(image.data() + jobs_bytes + items_bytes + queues_bytes + ctl_bytes, ptrs.data(),
                 ptrs.size() * sizeof(uintptr_t));
-  e = copy_on_own_stream(dev, b->d_mem, image.data(), used, hipMemcpyHostToDevice);
+  if (capture) {
+    e = copy_on_own_stream(dev, b->d_mem, image.data(), used, hipMemcpyHostToDevice);
+  } else {
+    // Without a graph the image waits in the block's pinned twin (made once
+    // per pooled block) and goes up on the first launch's stream.
+    if (!b->h_mem) e = hipHostMalloc(&b->h_mem, b->d_mem_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) {
+      std::memcpy(b->h_mem, image.data(), used);
+      b->upload_bytes = used;
+      b->upload_pending = true;
+      b->status_host = reinterpret_cast<uint32_t*>(static_cast<char*>(b->h_mem) + (used + 255) / 256 * 256);
+    } else {
+      b->h_mem = nullptr;
+    }
+  }
   if (e != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "batch descriptor upload");
@@ -1556,20 +1592,35 @@ int ntt_batch_launch(const ntt_batch* b, void* stream) {
   if (!b->exec) return fail(ZK_EINVAL, "batch was created without a graph; use ntt_batch_launch_eager");
   hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(batch)");
+  b->status_on_host = false;
   return mark_launched(b, static_cast<hipStream_t>(stream));
 }
 
 int ntt_batch_launch_eager(const ntt_batch* b, void* stream) {
   if (!b) return fail(ZK_EINVAL, "null batch");
-  if (int rc = batch_enqueue(b, static_cast<hipStream_t>(stream))) return rc;
-  return mark_launched(b, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = batch_enqueue(b, s)) return rc;
+  b->status_on_host = false;
+  if (b->status_host) {
+    // the error word follows the launch to the pinned twin, so that the
+    // status is read without a copy that could queue behind other streams
+    hipError_t e = hipMemcpyAsync(b->status_host, b->d_ctl + zk::kCtlError, sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "batch status copy");
+    b->status_on_host = true;
+  }
+  return mark_launched(b, s);
 }
 
 int ntt_batch_status(const ntt_batch* b) {
   if (!b) return fail(ZK_EINVAL, "null batch");
   uint32_t err = 0;
-  hipError_t e = copy_on_own_stream(b->device, &err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "batch status readback");
+  if (b->status_on_host) {
+    err = *static_cast<volatile const uint32_t*>(b->status_host);
+  } else {
+    hipError_t e = copy_on_own_stream(b->device, &err, b->d_ctl + zk::kCtlError, sizeof err, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch status readback");
+  }
   if (err & zk::kBatchErrWait)
     return fail(ZK_EDEVICE, "a batched dependency wait exceeded its poll limit; outputs are invalid");
   if (err) return fail(ZK_EDEVICE, "the batch ended with items not run; outputs are invalid");
@@ -1578,6 +1629,11 @@ int ntt_batch_status(const ntt_batch* b) {
 
 int ntt_batch_set_spin_limit(ntt_batch* b, uint32_t polls) {
   if (!b) return fail(ZK_EINVAL, "null batch");
+  if (b->upload_pending) {  // still in the host image: set it there
+    const size_t off = reinterpret_cast<char*>(b->d_ctl + zk::kCtlSpinLimit) - static_cast<char*>(b->d_mem);
+    std::memcpy(static_cast<char*>(b->h_mem) + off, &polls, sizeof polls);
+    return ZK_OK;
+  }
   hipError_t e = copy_on_own_stream(b->device, b->d_ctl + zk::kCtlSpinLimit, &polls, sizeof polls,
                                     hipMemcpyHostToDevice);
   return e == hipSuccess ? ZK_OK : hip_fail(e, "batch spin limit");
