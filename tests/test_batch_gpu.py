@@ -172,6 +172,44 @@ def test_forced_dependency_timeout_reports_error_and_recovers(c4, cuda):
     _check_all(bufs, [want[k] for k in sel], "after recovery")
 
 
+def test_eager_batch_status_from_host_and_recovery(c4, cuda):
+    """A batch without a graph uploads its work list on its first launch's
+    stream and copies its error word back on the launch stream: a spin limit
+    set before the first launch (still in the host image) makes the launch
+    fail and the status, read from host memory, says so; the limit restored
+    on the device, the next launch is correct.  A batch destroyed before any
+    launch frees its pending upload."""
+    import torch
+
+    from paper_2509_22684_amd._lib import (ntt_batch_create_jobs, ntt_batch_destroy, ntt_batch_launch_eager,
+                                           ntt_batch_set_spin_limit, ntt_batch_status, ntt_workspace_bytes)
+
+    jobs, plans, inputs, want = c4
+    sel = [k for k, j in enumerate(jobs) if j.log2n >= 14][:8]
+    job_plans = [plans[(jobs[k].field, jobs[k].log2n)] for k in sel]
+    ins = [inputs[k] for k in sel]
+    bufs = _fresh_bufs(ins, cuda)
+    # every job its own workspace (jobs of one batch run concurrently)
+    works = [torch.empty(max(1, ntt_workspace_bytes(p.handle) // 4), dtype=torch.int32, device=b.device)
+             for p, b in zip(job_plans, bufs)]
+    specs = [dict(plan=p, op="forward", out=b, work=w, **{"in": b}) for p, b, w in zip(job_plans, bufs, works)]
+    ntt_batch_destroy(ntt_batch_create_jobs(specs))  # never launched
+    h = ntt_batch_create_jobs(specs)
+    try:
+        ntt_batch_set_spin_limit(h, 0)
+        ntt_batch_launch_eager(h)
+        torch.cuda.synchronize()
+        assert ntt_batch_status(h) == -4
+        ntt_batch_set_spin_limit(h, 1 << 22)
+        _reset(bufs, ins)
+        ntt_batch_launch_eager(h)
+        torch.cuda.synchronize()
+        assert ntt_batch_status(h) == 0
+    finally:
+        ntt_batch_destroy(h)
+    _check_all(bufs, [want[k] for k in sel], "eager after recovery")
+
+
 def test_batch_rejects_unsupported_jobs(cuda):
     from paper_2509_22684_amd import Batch, Plan, ZkError
 
