@@ -191,6 +191,26 @@ __device__ __forceinline__ void mul2(Fq& r0, const Fq& a0, const Fq& b0, Fq& r1,
   r0 = r[0];
   r1 = r[1];
 }
+// Three and four independent products, interleaved: more instructions in
+// flight for the reduction's lone waves, where one product's chain of
+// dependent multiply-adds would otherwise wait on its own latency.
+__device__ __forceinline__ void mul3(Fq& r0, const Fq& a0, const Fq& b0, Fq& r1, const Fq& a1, const Fq& b1, Fq& r2,
+                                     const Fq& a2, const Fq& b2) {
+  Fq a[3] = {a0, a1, a2}, b[3] = {b0, b1, b2}, r[3];
+  mul_k<3>(r, a, b);
+  r0 = r[0];
+  r1 = r[1];
+  r2 = r[2];
+}
+__device__ __forceinline__ void mul4(Fq& r0, const Fq& a0, const Fq& b0, Fq& r1, const Fq& a1, const Fq& b1, Fq& r2,
+                                     const Fq& a2, const Fq& b2, Fq& r3, const Fq& a3, const Fq& b3) {
+  Fq a[4] = {a0, a1, a2, a3}, b[4] = {b0, b1, b2, b3}, r[4];
+  mul_k<4>(r, a, b);
+  r0 = r[0];
+  r1 = r[1];
+  r2 = r[2];
+  r3 = r[3];
+}
 __device__ __forceinline__ Fq sqr(const Fq& a) { return mul(a, a); }
 
 // a^-1 = a^(q-2) (Fermat), left-to-right square-and-multiply; a != 0.
