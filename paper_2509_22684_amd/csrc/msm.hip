@@ -124,15 +124,15 @@ __device__ __forceinline__ Xyzz add_mixed(const Xyzz& p, const Affine& a) {
   const Fq P = fq::sub(U2, p.X);
   const Fq R = fq::sub(S2, p.Y);
   if (fq::is_zero(P)) return fq::is_zero(R) ? dbl_affine(a) : infinity();
-  const Fq PP = fq::sqr(P);
+  Fq PP, RR;
+  fq::mul2(PP, P, P, RR, R, R);
   Fq PPP, Qx;
   fq::mul2(PPP, P, PP, Qx, p.X, PP);
   Xyzz r;
-  r.X = fq::sub(fq::sub(fq::sqr(R), PPP), fq::dbl(Qx));
+  r.X = fq::sub(fq::sub(RR, PPP), fq::dbl(Qx));
   Fq t, YP;
-  fq::mul2(t, R, fq::sub(Qx, r.X), YP, p.Y, PPP);
+  fq::mul4(t, R, fq::sub(Qx, r.X), YP, p.Y, PPP, r.ZZ, p.ZZ, PP, r.ZZZ, p.ZZZ, PPP);
   r.Y = fq::sub(t, YP);
-  fq::mul2(r.ZZ, p.ZZ, PP, r.ZZZ, p.ZZZ, PPP);
   return r;
 }
 
