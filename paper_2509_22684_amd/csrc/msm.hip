@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(kLevel0Lanes) bits_level0_kernel(const uint32_
 
 // G_b for b = blockIdx.x: the sum of the `len` level-0 results of bit b,
 // kReduceThreads lanes each summing a strided share, then a tree.
-constexpr int kReduceThreads = 128;
+constexpr int kReduceThreads = 64;  // one wave: at most 2^16 / (8 * 128) = 64 level-0 results per bit
 __global__ void __launch_bounds__(kReduceThreads) reduce_bit_kernel(const uint32_t* __restrict__ in, uint32_t len,
                                                                     uint32_t* __restrict__ out) {
   __shared__ Xyzz sh[kReduceThreads];
