@@ -5,13 +5,13 @@
 // reduction: 4q < 2^384, so a Montgomery product of two such elements is
 // below 2q without a final subtraction, and sums and differences reduce
 // modulo 2q); canon() brings one to [0, q) where it leaves the device.
-// FF_mul is the same finely integrated
-// product scanning as the scalar fields' (field.hpp): each 32x32-bit
-// partial product is one v_mad_u64_u32 into a 64-bit column accumulator
-// whose carry-out feeds a v_addc_co_u32 column counter, 2 N^2 = 288 of each
-// per product; K independent products interleave column by column, each
-// chain keeping its own carry SGPR pair.  FF_add / FF_sub are branchless
-// carry chains with a borrow-select.
+// FF_mul is the same finely integrated product scanning as the scalar
+// fields' (field.hpp): each 32x32-bit partial product is one v_mad_u64_u32
+// into a 64-bit column accumulator whose carry-out feeds a v_addc_co_u32
+// column counter, 2 N^2 = 288 of each per product; K independent products
+// (mul2, mul3, mul4) interleave column by column, each chain keeping its own
+// carry SGPR pair.  FF_add / FF_sub are branchless carry chains with a
+// borrow-select.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>

@@ -19,15 +19,15 @@
 // * Bucket accumulation: the sorted entries are cut into equal runs, one per
 //   lane, across bucket boundaries; a lane adds its run's points into XYZZ
 //   accumulators with mixed (XYZZ + affine) additions, 8 multiplications
-//   and 2 squarings each, and the segments at the runs' ends then combine
-//   per bucket.  XYZZ coordinates (x = X / ZZ, y = Y / ZZZ) keep additions
-//   free of inversions.
+//   and 2 squarings each in four rounds of independent products, and the
+//   segments at the runs' ends then combine per bucket.  XYZZ coordinates
+//   (x = X / ZZ, y = Y / ZZZ) keep additions free of inversions.
 // * Bucket reduction by bits: sum_k k B_k = sum_b 2^b G_b with
 //   G_b = sum of the buckets whose index has bit b set.  The G_b are
-//   independent reductions (chunks of buckets per lane, then a tree in LDS
-//   per bit), and the c terms 2^b G_b are doubled in parallel and summed by a
-//   tree: a critical path of a few dozen point operations, where the
-//   running-sum method is a serial chain of 2^(c+1) additions.
+//   independent reductions (chunk sums formed once, chunks per lane, then
+//   trees in LDS), and the c terms 2^b G_b are doubled in parallel and
+//   summed by a tree: a critical path of a few dozen point operations,
+//   where the running-sum method is a serial chain of 2^(c+1) additions.
 //
 // Field arithmetic: fq.hpp (12 x 32-bit limbs, Montgomery FIPS products).
 // Scalars arrive as the NTT library's Montgomery limbs over BLS12-381 Fr and
