@@ -271,6 +271,10 @@ typedef struct {
 } ntt_batch_job;
 
 #define ZK_BATCH_GRAPH 1 /* capture the launch into a HIP graph (ntt_batch_launch) */
+/* Every job as pass launches (transforms of equal plans grouped, pointwise
+ * steps on their own): no persistent kernel, whose large workgroups can wait
+ * long for room on CUs that other streams' pass kernels keep filling. */
+#define ZK_BATCH_DIRECT 2
 /* Work queues per field, 1..32 (0: 16).  Jobs are dealt largest first to the
  * least-loaded queue and each queue runs on one XCD: more queues balance the
  * XCDs more finely, fewer put more independent jobs in each queue so that a

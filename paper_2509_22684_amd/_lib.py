@@ -40,6 +40,7 @@ class _BatchJob(ctypes.Structure):
 OPS = {"forward": 0, "inverse": 1, "coset_forward": 2, "coset_inverse": 3, "inverse_to_coset": 4,
        "quotient_pointwise": 5}
 ZK_BATCH_GRAPH = 1
+ZK_BATCH_DIRECT = 2
 ZK_BATCH_QUEUES_SHIFT = 8
 
 _lib = None
@@ -489,9 +490,10 @@ def ntt_batch_create(plans, d_bufs, d_work=None) -> int:
     return h.value
 
 
-def ntt_batch_create_jobs(jobs, graph: bool = False, queues: int = 0) -> int:
+def ntt_batch_create_jobs(jobs, graph: bool = False, queues: int = 0, direct: bool = False) -> int:
     """jobs: dicts with keys plan, op (name or zk_op), in, out and optionally
-    in2, in3 (pointwise) and work.  queues: work queues per field (0: default)."""
+    in2, in3 (pointwise) and work.  queues: work queues per field (0: default);
+    direct: every job as pass launches, no persistent kernel."""
     arr = (_BatchJob * max(1, len(jobs)))()
     for k, j in enumerate(jobs):
         plan = j["plan"]
@@ -504,7 +506,7 @@ def ntt_batch_create_jobs(jobs, graph: bool = False, queues: int = 0) -> int:
         arr[k].out = _ptr(j.get("out"))
         arr[k].work = _ptr(j.get("work"))
     h = ctypes.c_void_p()
-    flags = (ZK_BATCH_GRAPH if graph else 0) | (int(queues) << ZK_BATCH_QUEUES_SHIFT)
+    flags = (ZK_BATCH_GRAPH if graph else 0) | (ZK_BATCH_DIRECT if direct else 0) | (int(queues) << ZK_BATCH_QUEUES_SHIFT)
     _check(lib().ntt_batch_create_jobs(ctypes.byref(h), arr, len(jobs), flags), "ntt_batch_create_jobs")
     return h.value
 

@@ -1145,7 +1145,7 @@ bool op_to_kind(int op, Kind* k) {
 }
 
 int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool capture,
-                size_t queues_per_field = kQueuesPerField) {
+                size_t queues_per_field = kQueuesPerField, bool all_direct = false) {
   if (!out) return fail(ZK_EINVAL, "null output pointer");
   *out = nullptr;
   if (njobs < 0 || (njobs > 0 && !specs)) return fail(ZK_EINVAL, "bad job array");
@@ -1252,7 +1252,7 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
   }
   std::vector<bool> direct(njobs, false);
   for (int k = 0; k < njobs; ++k)
-    if (jobs[k].kind == zk::kJobPointwise) direct[k] = load(k) * zk::kXcds > total;
+    if (jobs[k].kind == zk::kJobPointwise) direct[k] = all_direct || load(k) * zk::kXcds > total;
   constexpr double kLaunchUs = 4.0;      // gap between dependent launches
   constexpr double kRoundUs = 40.0;      // one round of 2^10-element pass tiles, 4 per CU
   constexpr double kBatchItemUs = 70.0;  // one 2^11-element item of the persistent kernel
@@ -1288,7 +1288,8 @@ int batch_build(ntt_batch** out, const ntt_batch_job* specs, int njobs, bool cap
     }
     return t + (it > 0 ? std::max(it * kBatchItemUs / batch_slots, alone) : 0.0);
   };
-  for (double best = estimate(G);;) {
+  if (all_direct) std::fill(moved.begin(), moved.end(), true);
+  for (double best = estimate(G); !all_direct;) {
     size_t pick = G;
     for (size_t g = 0; g < G; ++g) {
       if (moved[g]) continue;
@@ -1572,10 +1573,12 @@ int ntt_batch_create(ntt_batch** out, const ntt_plan* const* plans, void* const*
 }
 
 int ntt_batch_create_jobs(ntt_batch** out, const ntt_batch_job* jobs, int njobs, int flags) {
-  if (flags & ~(ZK_BATCH_GRAPH | ZK_BATCH_QUEUES_MASK)) return fail(ZK_EUNSUPPORTED, "unknown batch flag bits");
+  if (flags & ~(ZK_BATCH_GRAPH | ZK_BATCH_DIRECT | ZK_BATCH_QUEUES_MASK))
+    return fail(ZK_EUNSUPPORTED, "unknown batch flag bits");
   const size_t q = (size_t)((flags & ZK_BATCH_QUEUES_MASK) >> ZK_BATCH_QUEUES_SHIFT);
   if (q > (size_t)zk::kMaxLocalQueues) return fail(ZK_EUNSUPPORTED, "at most 32 queues per field");
-  return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0, q ? q : kQueuesPerField);
+  return batch_build(out, jobs, njobs, (flags & ZK_BATCH_GRAPH) != 0, q ? q : kQueuesPerField,
+                     (flags & ZK_BATCH_DIRECT) != 0);
 }
 
 // After every launch: the event that tells when the batch's descriptors

@@ -17,7 +17,10 @@ Fig. 3; Section IV-A) with each job's three independent chains side by side.
 Lanes.  Jobs are assigned by size to lanes, each with its own stream and its
 own sequence of ticks, so the long stages of large jobs (which fill the chip
 by themselves) do not hold back the next stage of small ones; the lanes'
-launches overlap on the device.
+launches overlap on the device.  A tick's batch runs as pass launches only
+(transforms of equal plans grouped into one launch per pass, ZK_BATCH_DIRECT):
+the batch's persistent kernel, whose workgroups are large, would wait for
+room on CUs that the other lane's pass kernels keep filling.
 
 A lone job runs whole.  When a lane holds a single job that has not
 started, its tick is that job's whole chain as one quotient_poly call (A's
@@ -184,7 +187,10 @@ class GpuExecutor:
                 stream.wait_event(h["ready"])
             jobs.extend(self._stage_jobs(h, stage))
         with self.torch.cuda.device(self.device):
-            b = ntt_batch_create_jobs(jobs)
+            # pass launches only: beside the other lanes' pass kernels the
+            # persistent kernel's large workgroups wait long for room on the
+            # CUs (p99 at rho = 0.5: 18 ms with it, 13-14 ms without)
+            b = ntt_batch_create_jobs(jobs, direct=True)
             try:
                 ntt_batch_launch_eager(b, stream)
             except Exception:
