@@ -210,6 +210,32 @@ def test_eager_batch_status_from_host_and_recovery(c4, cuda):
     _check_all(bufs, [want[k] for k in sel], "eager after recovery")
 
 
+def test_direct_batch_matches_oracle(c4, cuda):
+    """ZK_BATCH_DIRECT: every job of the 64-job workload as pass launches
+    (equal plans grouped, every other job a group of its own), no persistent
+    kernel: byte-identical to the oracle."""
+    import torch
+
+    from paper_2509_22684_amd._lib import (lib, ntt_batch_create_jobs, ntt_batch_destroy, ntt_batch_launch_eager,
+                                           ntt_batch_status, ntt_workspace_bytes)
+
+    jobs, plans, inputs, want = c4
+    job_plans = [plans[(j.field, j.log2n)] for j in jobs]
+    bufs = _fresh_bufs(inputs, cuda)
+    works = [torch.empty(max(1, ntt_workspace_bytes(p.handle) // 4), dtype=torch.int32, device=b.device)
+             for p, b in zip(job_plans, bufs)]
+    specs = [dict(plan=p, op="forward", out=b, work=w, **{"in": b}) for p, b, w in zip(job_plans, bufs, works)]
+    h = ntt_batch_create_jobs(specs, direct=True)
+    try:
+        assert lib().ntt_batch_items(h) == 0
+        ntt_batch_launch_eager(h)
+        torch.cuda.synchronize()
+        assert ntt_batch_status(h) == 0
+    finally:
+        ntt_batch_destroy(h)
+    _check_all(bufs, want, "direct")
+
+
 def test_batch_rejects_unsupported_jobs(cuda):
     from paper_2509_22684_amd import Batch, Plan, ZkError
 
