@@ -331,7 +331,7 @@ def serve_leg(dev, njobs: int = 256, rhos=(0.5, 0.8, 1.0, 1.25, 1.5)) -> dict:
     return {"workload": f"{njobs} quotient jobs, log2 n uniform in [14,22] (seed 5), BLS12-381 Fr, Poisson arrivals "
                         "at rho x solo throughput",
             "lanes": {"bounds_log2n": list(ex.lane_bounds), "ticks_enqueued_ahead": 2,
-                      "lone_job_runs_whole_chain": True},
+                      "lone_job_runs_whole_chain": True, "tick_batches": "pass launches only (ZK_BATCH_DIRECT)"},
             "mu_solo_jobs_per_s": mu, "solo_ms_by_log2n": {str(L): t * 1e3 for L, t in solo_s.items()},
             "runs": runs, "admission_2GB": admission}
 
